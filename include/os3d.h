@@ -1,0 +1,170 @@
+/*
+ * os3d: the discrete invertible 3D orientation-score transform with cake
+ * wavelets (Janssen, Duits & Breeuwer, "Invertible Orientation Scores of 3D
+ * Images"), on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every call returns an os3d_status (0 = OK) and never throws; the
+ * message of the last non-OK status of the calling thread is returned by
+ * os3d_last_error().
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - A volume is float32 [Nz][Ny][Nx] with x fastest (dims[] = {Nz, Ny, Nx}).
+ *   Every dim must be >= 2 and have no prime factor other than 2, 3 and 5
+ *   (others: OS3D_EUNSUPPORTED); the largest supported dim is 4096.
+ * - Orientations are float64 host arrays [N_o][3] of (x, y, z) unit vectors,
+ *   in the caller's order (the set V of Sec. 2.1).  Scores keep that order.
+ * - The DFT is unnormalised, F[k] = sum_x f[x] exp(-2 pi i k.x / N); its
+ *   inverse carries 1/V (V = Nz Ny Nx).  Frequencies are
+ *   omega_d = 2 pi kt_d / N_d, kt_d in [-N_d/2, N_d/2), Nyquist radius pi.
+ * - A score U is [B][N_o][Nz][Ny][Nx].  OS3D_C64 stores interleaved float32
+ *   (re, im).  OS3D_BF16X2 / OS3D_F16X2 store two 16-bit floats (re, im)
+ *   per voxel; the stored value times scales[b][i] (float32, a power of two)
+ *   is the score.
+ * - Device pointers are HIP device memory on the current device, owned by the
+ *   caller; the library never allocates device memory.  `stream` is a
+ *   hipStream_t passed as void* (NULL = the default stream).  Compute calls
+ *   only enqueue work on `stream` and return; os3d_build_bank synchronises
+ *   `stream` once at its end.
+ * - Argument errors are detected before any work is enqueued and return
+ *   OS3D_EINVAL; a failed launch returns OS3D_EDEVICE.
+ */
+#ifndef OS3D_H
+#define OS3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OS3D_OK = 0,
+  OS3D_EINVAL = -1,        /* invalid argument (null pointer, bad size, non-unit orientation, ...) */
+  OS3D_ENOMEM = -2,        /* a caller-provided buffer is smaller than required */
+  OS3D_EUNSUPPORTED = -3,  /* a dim with a prime factor other than 2, 3, 5, or above 4096 */
+  OS3D_EDEVICE = -4        /* a HIP runtime call or kernel launch failed */
+} os3d_status;
+
+typedef enum {
+  OS3D_C64 = 0,      /* complex float32, 8 B per voxel-orientation */
+  OS3D_BF16X2 = 1,   /* (re, im) bfloat16 pair times a per-(b, i) power-of-two scale, 4 B */
+  OS3D_F16X2 = 2     /* (re, im) IEEE half pair times a per-(b, i) power-of-two scale, 4 B */
+} os3d_score_dtype;
+
+typedef enum {
+  OS3D_CAKE = 0,     /* h = Funk(A) + antisym(A): real line detector, imaginary edge detector (Eqs. 12-14) */
+  OS3D_PLATE = 1     /* h = A: real plate detector (Sec. 3.1, Fig. 4) */
+} os3d_variant;
+
+/* Cake-wavelet parameters (Sec. 3).
+ *   L         spherical-harmonic order of the window expansion (Eq. 15), 0 <= L <= 64
+ *   s_theta   width of the orientation window A = B^k(theta / s_theta) (Eq. 11), > 0
+ *   k         B-spline order (Eq. 11), 0 <= k <= 16
+ *   taylor_N  Taylor order N of the radial window (Eq. 10), 0 <= N <= 200
+ *   gamma     inflection point of the radial window at gamma * rho_N (Sec. 3.1), 0 < gamma < 1
+ *   eps       floor in M -> max(M, eps) of the stabilised inverse (Sec. 3.1), > 0
+ *             (M vanishes on the Nyquist planes of even dims)
+ *   variant   os3d_variant */
+typedef struct {
+  int32_t L;
+  double s_theta;
+  int32_t k;
+  int32_t taylor_N;
+  double gamma;
+  double eps;
+  int32_t variant;
+} os3d_wavelet_params;
+
+/* Opaque host handle of a built bank: dims, orientation pairing, kappa and
+ * pointers into the caller's bank buffer.  Immutable after os3d_build_bank;
+ * calls on different streams may share it. */
+typedef struct os3d_bank os3d_bank;
+
+typedef struct {
+  int64_t dims[3];       /* Nz, Ny, Nx */
+  int32_t n_orients;     /* N_o */
+  int32_t n_unique;      /* stored bank rows: N_o/2 when the set is antipodally closed, else N_o */
+  int32_t paired;        /* 1 when every orientation has its antipode in the set */
+  double kappa;          /* normaliser: the band mean of M is 1 */
+  double M_min_band;     /* (reserved, 0) */
+  const float* M_dev;    /* M[k] on the device, frequency order of os3d_bank_M */
+} os3d_bank_info;
+
+/* Host-only wavelet design (Sec. 3.1-3.2), FP64, no device needed.
+ * c_out[0..L]: coefficients c_{l,0} of A fitted by least squares (the
+ * pseudo-inverse) over the frequency-15 geodesic icosahedron (Eq. 15);
+ * a_out[0..L]: coefficients of h (cake: 2 pi P_l(0) c_l + (1 - (-1)^l) c_l,
+ * Eqs. 12-16; plate: c_l).  Either output may be NULL. */
+os3d_status os3d_wavelet_coeffs(const os3d_wavelet_params* p, double* c_out, double* a_out);
+
+/* Host-only steering matrix (Eqs. 17-19 via the addition theorem), FP64:
+ * S_out[(l*l + l + m) * n_orients + i] = a_l sqrt(4 pi / (2l + 1)) Y_lm(n_i)
+ * for the library's real orthonormal spherical harmonics Y_lm,
+ * -l <= m <= l, so that sum_lm Y_lm(w) S[lm, i] = h(angle(w, n_i)).
+ * S_out holds (L+1)^2 * n_orients doubles. */
+os3d_status os3d_steering_matrix(const os3d_wavelet_params* p, const double* orients, int32_t n_orients,
+                                 double* S_out);
+
+/* Bytes of the device buffer a bank needs (bank rows, M, build scratch and
+ * constant tables). */
+os3d_status os3d_bank_bytes(const int64_t dims[3], const double* orients, int32_t n_orients,
+                            const os3d_wavelet_params* p, size_t* bytes);
+
+/* Builds the sampled bank psi_hat_i[k] = kappa g(rho_k) h(w_k . n_i) (real;
+ * Eqs. 10-19; 0 on Nyquist planes; a_0/sqrt(4 pi) at k = 0) and
+ * M[k] = sum_i psi_hat_i[k]^2 (Eq. 9, constants absorbed into kappa) into
+ * bank_dev (os3d_bank_bytes bytes, caller-owned, must outlive the handle).
+ * The contraction over spherical harmonics runs on the matrix cores.
+ * Synchronises `stream` at the end.  *out receives a new handle. */
+os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_t n_orients,
+                            const os3d_wavelet_params* p, void* bank_dev, size_t bank_bytes,
+                            void* stream, os3d_bank** out);
+
+/* Frees the host handle (not the caller's device buffer).  NULL is a no-op. */
+os3d_status os3d_free_bank(os3d_bank* bank);
+
+os3d_status os3d_get_bank_info(const os3d_bank* bank, os3d_bank_info* info);
+
+/* Writes psi_hat_i (float32 [Nz][Ny][Nx], natural DFT index order) of the
+ * caller's orientation i into psi_dev (device). */
+os3d_status os3d_bank_psi(const os3d_bank* bank, int32_t i, float* psi_dev, void* stream);
+
+/* Writes M (float32 [Nz][Ny][Nx], natural DFT index order) into M_dev (device). */
+os3d_status os3d_bank_M(const os3d_bank* bank, float* M_dev, void* stream);
+
+/* Bytes of workspace that os3d_forward / os3d_adjoint / os3d_reconstruct
+ * need for this bank (independent of the batch size and score dtype). */
+os3d_status os3d_workspace_bytes(const os3d_bank* bank, size_t* bytes);
+
+/* Discrete orientation score, Eq. (7): U[b][i] = IDFT(psi_hat_i DFT(f[b])),
+ * the circular correlation of f with conj(psi_i).
+ * f: device float32 [B][Nz][Ny][Nx]; U: device score (dtype as above);
+ * scales: device float32 [B][N_o] written for 16-bit dtypes (may be NULL for
+ * OS3D_C64); ws: device workspace of os3d_workspace_bytes bytes. */
+os3d_status os3d_forward(const os3d_bank* bank, const float* f, int32_t batch, void* U,
+                         int32_t dtype, float* scales, void* ws, size_t ws_bytes, void* stream);
+
+/* Real adjoint of os3d_forward (the orientation sum of Eq. (8) without the
+ * division by M): f_out[b] = Re IDFT(sum_i psi_hat_i DFT(U[b][i])).
+ * U may be any complex score (not only one produced by os3d_forward). */
+os3d_status os3d_adjoint(const os3d_bank* bank, const void* U, int32_t dtype, const float* scales,
+                         int32_t batch, float* f_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Stabilised exact reconstruction, Eq. (8) with M -> max(M, eps) (Sec. 3.1):
+ * f_out[b] = Re IDFT(sum_i psi_hat_i DFT(U[b][i]) / max(M, eps)). */
+os3d_status os3d_reconstruct(const os3d_bank* bank, const void* U, int32_t dtype, const float* scales,
+                             int32_t batch, float* f_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Message of the calling thread's last non-OK status ("" if none). */
+const char* os3d_last_error(void);
+
+/* Library version string. */
+const char* os3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OS3D_H */

@@ -1,0 +1,365 @@
+// Wavelet-bank synthesis on gfx950 (Sec. 3, Eqs. 9-19).
+//
+// For every DFT frequency k the rotated angular profiles of all stored bank
+// rows are one row of a dense contraction
+//     h[k, i] = sum_{(l,m)} Y_lm(w_hat_k) S[(l,m), i]
+// (S: steering matrix a_l sqrt(4 pi/(2l+1)) Y_lm(n_i), the addition-theorem
+// form of the Wigner-D rotation of Eqs. 17-19).  Each workgroup owns 256
+// frequency points: every thread generates its point's real spherical
+// harmonics for one order m at a time with the FP64 normalised associated
+// Legendre recursion, rounds them to FP32 into LDS, and the four waves run
+// v_mfma_f32_16x16x4_f32 over that K-chunk against S streamed from L2.  The
+// epilogue multiplies by the FP64 radial window g(rho) (Eq. 10), applies the
+// Nyquist and DC rules, writes the bank rows and accumulates
+// sum_i psi_i^2 (Eq. 9) in FP64 with a fixed-order cross-lane tree.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "os3d_internal.h"
+
+namespace os3d {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBankPts = 256;   // frequency points per workgroup
+constexpr int kYStride = 272;   // LDS row stride (floats) of the K-chunk buffer
+constexpr int kColsPerSweep = 128;
+
+struct BankArgs {
+  int Nz, Ny, Nx;
+  long long V;
+  int L, Npad, n_rows;
+  double t_inv;      // 1 / t of Eq. (10)
+  int taylor_N;
+  double dc_value;   // a_0 / sqrt(4 pi)
+  const float* S;    // [K][Npad]
+  const double* tab; // qmm[L+1] | alm[(L+1)^2] | blm[(L+1)^2]
+  const int* koff;   // chunk offsets [L+1] | padded lengths [L+1]
+  float* psi;        // [n_rows][V]
+  double* Mh;        // [V]
+};
+
+__device__ inline double omega_of(int k, int n) {
+  int kt = (k < (n + 1) / 2) ? k : k - n;
+  return 2.0 * 3.14159265358979323846 * (double)kt / (double)n;
+}
+
+__device__ inline bool is_nyquist(int k, int n) { return (n % 2 == 0) && (k == n / 2); }
+
+// Radial window of Eq. (10): exp(-x) sum_{j <= N} x^j / j!, x = rho^2 / t.
+__device__ inline double radial_g(double rho2, double t_inv, int N) {
+  double x = rho2 * t_inv;
+  double term = exp(-x), acc = term;
+  for (int j = 1; j <= N; ++j) {
+    term = term * x / (double)j;
+    acc += term;
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
+  extern __shared__ float Ybuf[];  // [kchunk_max][kYStride]
+  __shared__ double gsh[kBankPts];
+  __shared__ int dcsh[kBankPts];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const long long p0 = (long long)blockIdx.x * kBankPts;
+  const long long p = p0 + tid;
+  const bool valid = p < a.V;
+  const int L = a.L, nn = L + 1;
+  const double* qmm = a.tab;
+  const double* alm = a.tab + nn;
+  const double* blm = a.tab + nn + nn * nn;
+  const int* koff = a.koff;
+  const int* kpad = a.koff + nn;
+
+  // this thread's frequency point
+  double ux = 0.0, uy = 0.0, uz = 1.0, g = 0.0;
+  int dc = 0;
+  if (valid) {
+    int kx = (int)(p % a.Nx);
+    int ky = (int)((p / a.Nx) % a.Ny);
+    int kz = (int)(p / ((long long)a.Nx * a.Ny));
+    double wx = omega_of(kx, a.Nx), wy = omega_of(ky, a.Ny), wz = omega_of(kz, a.Nz);
+    double r2 = wx * wx + wy * wy + wz * wz;
+    if (r2 > 0.0) {
+      double r = sqrt(r2);
+      ux = wx / r;
+      uy = wy / r;
+      uz = wz / r;
+    } else {
+      dc = 1;
+    }
+    bool nyq = is_nyquist(kx, a.Nx) || is_nyquist(ky, a.Ny) || is_nyquist(kz, a.Nz);
+    g = nyq ? 0.0 : radial_g(r2, a.t_inv, a.taylor_N);
+  }
+  gsh[tid] = g;
+  dcsh[tid] = dc;
+
+  double mh[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int i = 0; i < 4; ++i) mh[r][i] = 0.0;
+
+  for (int c0 = 0; c0 < a.Npad; c0 += kColsPerSweep) {
+    const int ncb = min(kColsPerSweep, a.Npad - c0) / 16;
+    floatx4 acc[4][8];
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 8; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    double cr = 1.0, ci = 0.0;  // (x + i y)^m of the unit frequency direction
+    for (int m = 0; m <= L; ++m) {
+      if (m > 0) {
+        double nr = cr * ux - ci * uy, ni = cr * uy + ci * ux;
+        cr = nr;
+        ci = ni;
+      }
+      const int len = (m == 0) ? nn : 2 * (nn - m);
+      const int pad = kpad[m];
+      // generate chunk m: Q_l^m for l = m..L (sinus power factored out)
+      {
+        double q2 = 0.0, q1 = qmm[m];
+        const double s2 = 1.4142135623730950488;
+        for (int l = m; l <= L; ++l) {
+          double q;
+          if (l == m)
+            q = qmm[m];
+          else if (l == m + 1)
+            q = sqrt(2.0 * m + 3.0) * uz * qmm[m];
+          else
+            q = alm[l * nn + m] * (uz * q1 - blm[l * nn + m] * q2);
+          if (l > m) q2 = q1;
+          q1 = q;
+          if (m == 0) {
+            Ybuf[(l)*kYStride + tid] = (float)q;
+          } else {
+            Ybuf[(l - m) * kYStride + tid] = (float)(s2 * q * cr);
+            Ybuf[(nn - m + l - m) * kYStride + tid] = (float)(s2 * q * ci);
+          }
+        }
+        for (int kk = len; kk < pad; ++kk) Ybuf[kk * kYStride + tid] = 0.f;
+      }
+      __syncthreads();
+      const float* Sm = a.S + (long long)koff[m] * a.Npad + c0;
+      for (int k0 = 0; k0 < pad; k0 += 4) {
+        const int kr = k0 + (lane >> 4);
+        float af[4];
+        for (int r = 0; r < 4; ++r) af[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
+        const float* Sr = Sm + (long long)kr * a.Npad + (lane & 15);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          if (c < ncb) {
+            float bf = Sr[c * 16];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[r], bf, acc[r][c], 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // epilogue: psi_raw = g * h (DC: isotropic), bank rows, FP64 sum of squares
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (c >= ncb) continue;
+      const int col = c0 + c * 16 + (lane & 15);
+      const bool colok = col < a.n_rows;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pt = wave * 64 + r * 16 + 4 * (lane >> 4) + i;
+          const long long gp = p0 + pt;
+          double h = dcsh[pt] ? a.dc_value : (double)acc[r][c][i];
+          float v = (float)(gsh[pt] * h);
+          if (colok && gp < a.V) a.psi[(long long)col * a.V + gp] = v;
+          if (colok) mh[r][i] += (double)v * (double)v;
+        }
+      }
+    }
+  }
+
+  // sum over the 16 lanes that share (lane >> 4): fixed xor tree
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double s = mh[r][i];
+      s += __shfl_xor(s, 1);
+      s += __shfl_xor(s, 2);
+      s += __shfl_xor(s, 4);
+      s += __shfl_xor(s, 8);
+      mh[r][i] = s;
+    }
+  if ((lane & 15) == 0) {
+    for (int r = 0; r < 4; ++r)
+      for (int i = 0; i < 4; ++i) {
+        const long long gp = p0 + wave * 64 + r * 16 + 4 * (lane >> 4) + i;
+        if (gp < a.V) a.Mh[gp] = mh[r][i];
+      }
+  }
+}
+
+// S: k -> -k mod N on every axis.
+__device__ inline long long mirror_index(long long p, int Nz, int Ny, int Nx) {
+  int kx = (int)(p % Nx);
+  int ky = (int)((p / Nx) % Ny);
+  int kz = (int)(p / ((long long)Nx * Ny));
+  kx = (Nx - kx) % Nx;
+  ky = (Ny - ky) % Ny;
+  kz = (Nz - kz) % Nz;
+  return ((long long)kz * Ny + ky) * Nx + kx;
+}
+
+// Partial sums over the band (rho <= rho_N / 2, no Nyquist plane, k != 0) of
+// the un-normalised M0[k] = Mh[k] (+ Mh[-k] for antipodal pairs).
+__global__ __launch_bounds__(256) void k_kappa_partial(const double* Mh, int paired, int Nz, int Ny, int Nx,
+                                                       long long V, double* part) {
+  __shared__ double ssum[256];
+  __shared__ double scnt[256];
+  const int tid = threadIdx.x;
+  const long long chunk = (V + gridDim.x - 1) / gridDim.x;
+  const long long b = (long long)blockIdx.x * chunk, e = min(V, b + chunk);
+  double s = 0.0, cnt = 0.0;
+  const double half = 0.5 * 3.14159265358979323846;
+  for (long long p = b + tid; p < e; p += 256) {
+    int kx = (int)(p % Nx);
+    int ky = (int)((p / Nx) % Ny);
+    int kz = (int)(p / ((long long)Nx * Ny));
+    if (is_nyquist(kx, Nx) || is_nyquist(ky, Ny) || is_nyquist(kz, Nz)) continue;
+    double wx = omega_of(kx, Nx), wy = omega_of(ky, Ny), wz = omega_of(kz, Nz);
+    double rho = sqrt(wx * wx + wy * wy + wz * wz);
+    if (rho > 0.0 && rho <= half) {
+      double m0 = Mh[p] + (paired ? Mh[mirror_index(p, Nz, Ny, Nx)] : 0.0);
+      s += m0;
+      cnt += 1.0;
+    }
+  }
+  ssum[tid] = s;
+  scnt[tid] = cnt;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      ssum[tid] += ssum[tid + w];
+      scnt[tid] += scnt[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[2 * blockIdx.x] = ssum[0];
+    part[2 * blockIdx.x + 1] = scnt[0];
+  }
+}
+
+__global__ void k_kappa_final(double* part, int nparts) {
+  if (threadIdx.x == 0) {
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < nparts; ++i) {
+      s += part[2 * i];
+      c += part[2 * i + 1];
+    }
+    part[2 * nparts] = (c > 0.0 && s > 0.0) ? 1.0 / sqrt(s / c) : 1.0;
+  }
+}
+
+// psi *= kappa; M = kappa^2 M0.
+__global__ __launch_bounds__(256) void k_bank_finalize(float* psi, int n_rows, double* Mh, float* M, int paired,
+                                                       int Nz, int Ny, int Nx, long long V, const double* kappa_p) {
+  const double kappa = *kappa_p;
+  const float kf = (float)kappa;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < V; p += stride) {
+    double m0 = Mh[p] + (paired ? Mh[mirror_index(p, Nz, Ny, Nx)] : 0.0);
+    M[p] = (float)(kappa * kappa * m0);
+    for (int r = 0; r < n_rows; ++r) psi[(long long)r * V + p] *= kf;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_export_psi(const float* row, int mirrored, int Nz, int Ny, int Nx, long long V,
+                                                    float* out) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < V; p += stride)
+    out[p] = row[mirrored ? mirror_index(p, Nz, Ny, Nx) : p];
+}
+
+static int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return OS3D_EDEVICE;
+  }
+  return OS3D_OK;
+}
+
+int launch_build_bank(os3d_bank* b, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int L = b->L, nn = L + 1;
+  BankArgs a;
+  a.Nz = (int)b->dims[0];
+  a.Ny = (int)b->dims[1];
+  a.Nx = (int)b->dims[2];
+  a.V = b->V;
+  a.L = L;
+  a.Npad = b->Npad;
+  a.n_rows = b->n_unique;
+  const double rhoN = 3.14159265358979323846;
+  const double t = 2.0 * (b->params.gamma * rhoN) * (b->params.gamma * rhoN) / (1.0 + 2.0 * b->params.taylor_N);
+  a.t_inv = 1.0 / t;
+  a.taylor_N = b->params.taylor_N;
+  a.S = b->d.S;
+  a.tab = b->d.tab;
+  a.koff = (const int*)(b->d.tab + nn + 2 * nn * nn);
+  a.psi = b->d.psi;
+  a.Mh = b->d.Mh;
+  a.dc_value = b->dc_value;
+  int maxpad = 0;
+  using std::max;
+  KLayout kl = k_layout(L);
+  for (int m = 0; m <= L; ++m) maxpad = max(maxpad, kl.pad[m]);
+  size_t lds = (size_t)maxpad * kYStride * sizeof(float);
+  const long long nblk = (b->V + kBankPts - 1) / kBankPts;
+  if (hipFuncSetAttribute((const void*)k_bank_synth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+      hipSuccess) {
+    set_error("k_bank_synth: cannot reserve LDS");
+    return OS3D_EDEVICE;
+  }
+  hipLaunchKernelGGL(k_bank_synth, dim3((unsigned)nblk), dim3(256), lds, st, a);
+  int rc = check_launch("k_bank_synth");
+  if (rc) return rc;
+  const int nparts = 1024;
+  hipLaunchKernelGGL(k_kappa_partial, dim3(nparts), dim3(256), 0, st, b->d.Mh, b->paired, a.Nz, a.Ny, a.Nx, a.V,
+                     b->d.part);
+  if ((rc = check_launch("k_kappa_partial"))) return rc;
+  hipLaunchKernelGGL(k_kappa_final, dim3(1), dim3(64), 0, st, b->d.part, nparts);
+  if ((rc = check_launch("k_kappa_final"))) return rc;
+  const unsigned fin_blocks = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_bank_finalize, dim3(fin_blocks), dim3(256), 0, st, b->d.psi, b->n_unique, b->d.Mh, b->d.M,
+                     b->paired, a.Nz, a.Ny, a.Nx, a.V, b->d.part + 2 * nparts);
+  if ((rc = check_launch("k_bank_finalize"))) return rc;
+  double kappa = 0.0;
+  if (hipMemcpyAsync(&kappa, b->d.part + 2 * nparts, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    set_error("os3d_build_bank: reading kappa failed");
+    return OS3D_EDEVICE;
+  }
+  b->kappa = kappa;
+  return OS3D_OK;
+}
+
+int launch_export_psi(const os3d_bank* b, int i, float* out, void* stream) {
+  const float* row = b->d.psi + (long long)b->row_of[i] * b->V;
+  const unsigned nb = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_export_psi, dim3(nb), dim3(256), 0, (hipStream_t)stream, row, b->conj_of[i], (int)b->dims[0],
+                     (int)b->dims[1], (int)b->dims[2], b->V, out);
+  return check_launch("k_export_psi");
+}
+
+int launch_export_M(const os3d_bank* b, float* out, void* stream) {
+  if (hipMemcpyAsync(out, b->d.M, b->V * sizeof(float), hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess) {
+    set_error("os3d_bank_M: copy failed");
+    return OS3D_EDEVICE;
+  }
+  return OS3D_OK;
+}
+
+}  // namespace os3d

@@ -1,0 +1,554 @@
+// 3D DFT passes of the orientation-score transform (Eqs. 7-8) on gfx950.
+//
+// A pass computes the length-N DFT of every line of a volume along one axis.
+// A workgroup owns W consecutive lines (W * N <= 4096): it stages them in
+// LDS with coalesced global accesses (x-lines are contiguous; y- and z-lines
+// are read as W consecutive x positions per row), runs the mixed-radix
+// Stockham stages (radix 16, 8, 4, 2, 5, 3) between two LDS buffers, and
+// writes the lines back.  The first and last pass of each 3D transform fuse
+// the per-voxel work of the method into their global loads and stores:
+//   * spectral multiply psi_hat_i * F (forward, Eq. 7),
+//   * antipodal pair store U_n and U_{-n} = conj(U_n), optionally rounded to
+//     16-bit pairs with a per-orientation power-of-two scale,
+//   * pair load U_n + conj(U_{-n}) and the weighted orientation sum
+//     X += psi_hat_n * DFT(.) over a batch of pairs (Eq. 8),
+//   * X / max(M, eps) (Sec. 3.1) and the real part of the inverse.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+
+#include "fft_radix.h"
+#include "os3d_internal.h"
+
+namespace os3d {
+
+constexpr int kThreads = 256;
+constexpr int kTile = 4096;      // complex elements per workgroup tile
+constexpr int kEPT = kTile / kThreads;
+constexpr int kMaxBatch = 16;    // orientation pairs per launch
+
+enum LoadMode { LM_REAL = 0, LM_C = 1, LM_MULBANK = 2, LM_UIN = 3, LM_DIVM = 4 };
+enum StoreMode { SM_C = 0, SM_UOUT = 1, SM_ACCUM = 2, SM_REAL = 3 };
+
+struct PassArgs {
+  int axis;  // 0 = z, 1 = y, 2 = x
+  int Nz, Ny, Nx;
+  long long V;
+  int N, nst;
+  int radix[kMaxStages];
+  int W, LS;            // lines per tile, LDS line stride (float2)
+  long long lines;      // V / N
+  const float2* tw;     // exp(-2 pi i j / N)
+  float sgn;            // -1: forward DFT, +1: inverse DFT
+  int nb;               // pairs in this launch
+  // sources
+  const float* src_r;
+  const float2* src_c;
+  long long src_stride;  // per pair (elements)
+  const float* psi;      // bank rows
+  int rows[kMaxBatch];
+  int oa[kMaxBatch], ob[kMaxBatch];  // stored member, partner (-1 if none)
+  const void* U;
+  int dtype;
+  const float* scales;   // [N_o] of this volume
+  const float* M;
+  float eps;
+  int divide;
+  // destinations
+  float2* dst_c;
+  long long dst_stride;
+  float* dst_r;
+  void* Uout;
+  float out_scale;
+  float* partial;        // [nb][tiles] sums of |value| (scale bound), or null
+  int accumulate;        // SM_ACCUM: 1 adds to X, 0 overwrites
+};
+
+__device__ __forceinline__ long long gaddr(const PassArgs& a, long long line, int n) {
+  if (a.axis == 2) return line * a.Nx + n;
+  if (a.axis == 1) {
+    long long z = line / a.Nx, x = line - z * a.Nx;
+    return (z * a.Ny + n) * a.Nx + x;
+  }
+  return (long long)n * a.Ny * a.Nx + line;
+}
+
+__device__ __forceinline__ int lidx(int LS, int w, int n) { return w * LS + n + (n >> 4); }
+
+__device__ __forceinline__ float2 load_score(const void* U, int dtype, long long i, float s) {
+  if (dtype == OS3D_C64) return ((const float2*)U)[i];
+  const unsigned int q = ((const unsigned int*)U)[i];
+  float re, im;
+  if (dtype == OS3D_F16X2) {
+    re = __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
+    im = __half2float(__ushort_as_half((unsigned short)(q >> 16)));
+  } else {
+    re = __uint_as_float((q & 0xffffu) << 16);
+    im = __uint_as_float(q & 0xffff0000u);
+  }
+  return make_float2(re * s, im * s);
+}
+
+__device__ __forceinline__ unsigned int bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  unsigned int lsb = (u >> 16) & 1u;
+  return (u + 0x7fffu + lsb) >> 16;
+}
+
+__device__ __forceinline__ void store_score(void* U, int dtype, long long i, float2 v, float inv_s) {
+  if (dtype == OS3D_C64) {
+    ((float2*)U)[i] = v;
+    return;
+  }
+  float re = v.x * inv_s, im = v.y * inv_s;
+  unsigned int q;
+  if (dtype == OS3D_F16X2)
+    q = (unsigned int)__half_as_ushort(__float2half_rn(re)) | ((unsigned int)__half_as_ushort(__float2half_rn(im)) << 16);
+  else
+    q = bf16_rne(re) | (bf16_rne(im) << 16);
+  ((unsigned int*)U)[i] = q;
+}
+
+template <int R>
+__device__ __forceinline__ void stage(const PassArgs& a, const float2* __restrict__ cur, float2* __restrict__ nxt,
+                                      int Ns, int nl) {
+  const int N = a.N, NR = N / R, tstep = N / (Ns * R);
+  const int total = a.W * NR;
+  for (int b = threadIdx.x; b < total; b += kThreads) {
+    const int w = b / NR, j = b - w * NR;
+    if (w >= nl) continue;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = cur[lidx(a.LS, w, j + r * NR)];
+    const int k = j % Ns;
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 t = a.tw[k * r * tstep];
+        if (a.sgn > 0.f) t.y = -t.y;
+        v[r] = cmul(v[r], t);
+      }
+    }
+    dft_r<R>(v, a.sgn);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) nxt[lidx(a.LS, w, base + r * Ns)] = v[r];
+  }
+}
+
+template <int LM, int SM>
+__global__ __launch_bounds__(kThreads) void k_pass(PassArgs a) {
+  extern __shared__ float2 lds[];
+  __shared__ float red[kThreads];
+  const int tile = blockIdx.x;
+  const long long line0 = (long long)tile * a.W;
+  const int nl = (int)min((long long)a.W, a.lines - line0);
+  const int tsize = a.W * a.N;
+  const bool contiguous = (a.axis == 2);
+  const int bufsz = a.W * a.LS;
+  float2* buf0 = lds;
+  float2* buf1 = lds + bufsz;
+
+  // SM_ACCUM walks the whole pair batch inside one workgroup; other modes take
+  // their pair from blockIdx.y.
+  const int jb = (SM == SM_ACCUM) ? 0 : blockIdx.y;
+  const int je = (SM == SM_ACCUM) ? a.nb : blockIdx.y + 1;
+  float2 acc[kEPT];
+#pragma unroll
+  for (int e = 0; e < kEPT; ++e) acc[e] = make_float2(0.f, 0.f);
+
+  for (int j = jb; j < je; ++j) {
+    // ---------------------------------------------------------------- load
+    float asum = 0.f;
+#pragma unroll
+    for (int e = 0; e < kEPT; ++e) {
+      const int idx = threadIdx.x + e * kThreads;
+      if (idx < tsize) {
+        int w, n;
+        if (contiguous) {
+          w = idx / a.N;
+          n = idx - w * a.N;
+        } else {
+          n = idx / a.W;
+          w = idx - n * a.W;
+        }
+        if (w < nl) {
+          const long long g = gaddr(a, line0 + w, n);
+          float2 v;
+          if constexpr (LM == LM_REAL) {
+            v = make_float2(a.src_r[g], 0.f);
+          } else if constexpr (LM == LM_C) {
+            v = a.src_c[j * a.src_stride + g];
+          } else if constexpr (LM == LM_MULBANK) {
+            const float p = a.psi[(long long)a.rows[j] * a.V + g];
+            v = cscale(a.src_c[g], p);
+            asum += sqrtf(v.x * v.x + v.y * v.y);
+          } else if constexpr (LM == LM_UIN) {
+            const int ia = a.oa[j], ib = a.ob[j];
+            const float sa = a.scales ? a.scales[ia] : 1.f;
+            v = load_score(a.U, a.dtype, (long long)ia * a.V + g, sa);
+            if (ib >= 0) {
+              const float sb = a.scales ? a.scales[ib] : 1.f;
+              v = cadd(v, cconj(load_score(a.U, a.dtype, (long long)ib * a.V + g, sb)));
+            }
+          } else {  // LM_DIVM
+            v = a.src_c[g];
+            if (a.divide) v = cscale(v, 1.f / fmaxf(a.M[g], a.eps));
+          }
+          buf0[lidx(a.LS, w, n)] = v;
+        }
+      }
+    }
+    if constexpr (LM == LM_MULBANK) {
+      if (a.partial) {
+        red[threadIdx.x] = asum;
+        __syncthreads();
+        for (int s = kThreads / 2; s > 0; s >>= 1) {
+          if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+          __syncthreads();
+        }
+        if (threadIdx.x == 0) a.partial[(long long)j * gridDim.x + tile] = red[0];
+      }
+    }
+    __syncthreads();
+
+    // -------------------------------------------------------------- stages
+    float2* cur = buf0;
+    float2* nxt = buf1;
+    int Ns = 1;
+    for (int s = 0; s < a.nst; ++s) {
+      const int R = a.radix[s];
+      switch (R) {
+        case 16: stage<16>(a, cur, nxt, Ns, nl); break;
+        case 8: stage<8>(a, cur, nxt, Ns, nl); break;
+        case 4: stage<4>(a, cur, nxt, Ns, nl); break;
+        case 2: stage<2>(a, cur, nxt, Ns, nl); break;
+        case 5: stage<5>(a, cur, nxt, Ns, nl); break;
+        default: stage<3>(a, cur, nxt, Ns, nl); break;
+      }
+      __syncthreads();
+      float2* t = cur;
+      cur = nxt;
+      nxt = t;
+      Ns *= R;
+    }
+
+    // --------------------------------------------------------------- store
+#pragma unroll
+    for (int e = 0; e < kEPT; ++e) {
+      const int idx = threadIdx.x + e * kThreads;
+      if (idx < tsize) {
+        int w, n;
+        if (contiguous) {
+          w = idx / a.N;
+          n = idx - w * a.N;
+        } else {
+          n = idx / a.W;
+          w = idx - n * a.W;
+        }
+        if (w < nl) {
+          const long long g = gaddr(a, line0 + w, n);
+          const float2 v = cur[lidx(a.LS, w, n)];
+          if constexpr (SM == SM_C) {
+            a.dst_c[j * a.dst_stride + g] = v;
+          } else if constexpr (SM == SM_UOUT) {
+            const float2 u = cscale(v, a.out_scale);
+            const int ia = a.oa[j], ib = a.ob[j];
+            const float inv_s = a.scales ? 1.f / a.scales[ia] : 1.f;
+            store_score(a.Uout, a.dtype, (long long)ia * a.V + g, u, inv_s);
+            if (ib >= 0) store_score(a.Uout, a.dtype, (long long)ib * a.V + g, cconj(u), inv_s);
+          } else if constexpr (SM == SM_ACCUM) {
+            const float p = a.psi[(long long)a.rows[j] * a.V + g];
+            acc[e] = make_float2(acc[e].x + p * v.x, acc[e].y + p * v.y);
+          } else {  // SM_REAL
+            a.dst_r[g] = v.x * a.out_scale;
+          }
+        }
+      }
+    }
+    if constexpr (SM == SM_ACCUM) __syncthreads();  // buf0 is reloaded for the next pair
+  }
+
+  if constexpr (SM == SM_ACCUM) {
+#pragma unroll
+    for (int e = 0; e < kEPT; ++e) {
+      const int idx = threadIdx.x + e * kThreads;
+      if (idx < tsize) {
+        int w, n;
+        if (contiguous) {
+          w = idx / a.N;
+          n = idx - w * a.N;
+        } else {
+          n = idx / a.W;
+          w = idx - n * a.W;
+        }
+        if (w < nl) {
+          const long long g = gaddr(a, line0 + w, n);
+          float2 x = acc[e];
+          if (a.accumulate) x = cadd(a.dst_c[g], x);
+          a.dst_c[g] = x;
+        }
+      }
+    }
+  }
+}
+
+// Per-orientation power-of-two scale for 16-bit score storage from the
+// bound max|U_i| <= (1/V) sum_k |psi_hat_i[k] F[k]|: fp16 maps the bound to
+// at most 2^15, bf16 to at most 1.  Fixed-order FP64 sum (deterministic).
+__global__ __launch_bounds__(256) void k_scales(const float* partial, int ntiles, PassArgs a, int dtype,
+                                                float* scales) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int t = threadIdx.x; t < ntiles; t += 256) s += (double)partial[(long long)j * ntiles + t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double bound = red[0] / (double)a.V * (1.0 + 1e-5);
+    float sc = 1.f;
+    if (bound > 0.0) {
+      int e;
+      frexp(bound, &e);  // bound <= 2^e
+      sc = (float)ldexp(1.0, dtype == OS3D_F16X2 ? e - 15 : e);
+    }
+    scales[a.oa[j]] = sc;
+    if (a.ob[j] >= 0) scales[a.ob[j]] = sc;
+  }
+}
+
+static int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return OS3D_EDEVICE;
+  }
+  return OS3D_OK;
+}
+
+static void setup_axis(const os3d_bank* b, int axis, PassArgs& a) {
+  a.axis = axis;
+  a.Nz = (int)b->dims[0];
+  a.Ny = (int)b->dims[1];
+  a.Nx = (int)b->dims[2];
+  a.V = b->V;
+  const AxisPlan& p = b->plan[axis];
+  a.N = p.n;
+  a.nst = p.nstages;
+  for (int s = 0; s < kMaxStages; ++s) a.radix[s] = (s < p.nstages) ? p.radix[s] : 0;
+  a.W = std::min(256, std::max(1, kTile / a.N));
+  a.LS = a.N + (a.N >> 4) + 1;
+  a.lines = a.V / a.N;
+  a.tw = (const float2*)b->d.tw[axis];
+}
+
+static size_t pass_lds(const PassArgs& a) { return (size_t)2 * a.W * a.LS * sizeof(float2); }
+
+template <int LM, int SM>
+static int run_pass(const PassArgs& a, int grid_y, hipStream_t st) {
+  const long long tiles = (a.lines + a.W - 1) / a.W;
+  const size_t lds = pass_lds(a);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_pass<LM, SM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_pass<LM, SM>), dim3((unsigned)tiles, grid_y), dim3(kThreads), lds, st, a);
+  return check_launch("k_pass");
+}
+
+static int pair_batch(const os3d_bank* b) {
+  int nb = 8;
+  if (const char* e = getenv("OS3D_PAIR_BATCH")) nb = atoi(e);
+  return std::max(1, std::min(std::min(nb, kMaxBatch), b->n_unique));
+}
+
+size_t workspace_bytes(const os3d_bank* b) {
+  const int nb = pair_batch(b);
+  long long max_tiles = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = b->plan[ax].n;
+    const int W = std::min(256, std::max(1, kTile / n));
+    max_tiles = std::max(max_tiles, (long long)((b->V / n + W - 1) / W));
+  }
+  return (size_t)(1 + nb) * b->V * sizeof(float2) + (size_t)nb * max_tiles * sizeof(float) + 256;
+}
+
+// forward DFT of one real volume into F (three passes, in place after the first)
+static int dft_real_volume(const os3d_bank* b, const float* f, float2* F, hipStream_t st) {
+  int rc;
+  PassArgs a = {};
+  setup_axis(b, 2, a);
+  a.sgn = -1.f;
+  a.nb = 1;
+  a.src_r = f;
+  a.dst_c = F;
+  if ((rc = run_pass<LM_REAL, SM_C>(a, 1, st))) return rc;
+  for (int ax : {1, 0}) {
+    PassArgs c = {};
+    setup_axis(b, ax, c);
+    c.sgn = -1.f;
+    c.nb = 1;
+    c.src_c = F;
+    c.dst_c = F;
+    if ((rc = run_pass<LM_C, SM_C>(c, 1, st))) return rc;
+  }
+  return OS3D_OK;
+}
+
+int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int dtype, float* scales, void* ws,
+                   void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const long long V = b->V;
+  const int nbmax = pair_batch(b);
+  float2* F = (float2*)ws;
+  float2* T = F + V;
+  float* partial = (float*)(T + (long long)nbmax * V);
+  const size_t ubytes = (dtype == OS3D_C64) ? 8 : 4;
+  int rc;
+  for (int bi = 0; bi < batch; ++bi) {
+    if ((rc = dft_real_volume(b, f + (long long)bi * V, F, st))) return rc;
+    void* Ub = (char*)U + (size_t)bi * b->n_orients * V * ubytes;
+    float* sc = scales ? scales + (long long)bi * b->n_orients : nullptr;
+    for (int r0 = 0; r0 < b->n_unique; r0 += nbmax) {
+      const int nb = std::min(nbmax, b->n_unique - r0);
+      PassArgs z = {};
+      setup_axis(b, 0, z);
+      z.sgn = 1.f;
+      z.nb = nb;
+      for (int j = 0; j < nb; ++j) {
+        const int o = b->rep[r0 + j];
+        z.rows[j] = r0 + j;
+        z.oa[j] = o;
+        z.ob[j] = b->partner[o];
+      }
+      z.src_c = F;
+      z.psi = b->d.psi;
+      z.dst_c = T;
+      z.dst_stride = V;
+      const bool quant = dtype != OS3D_C64;
+      z.partial = quant ? partial : nullptr;
+      if ((rc = run_pass<LM_MULBANK, SM_C>(z, nb, st))) return rc;
+      if (quant) {
+        const long long tiles = (z.lines + z.W - 1) / z.W;
+        hipLaunchKernelGGL(k_scales, dim3(nb), dim3(256), 0, st, partial, (int)tiles, z, dtype, sc);
+        if ((rc = check_launch("k_scales"))) return rc;
+      }
+      PassArgs y = {};
+      setup_axis(b, 1, y);
+      y.sgn = 1.f;
+      y.nb = nb;
+      y.src_c = T;
+      y.src_stride = V;
+      y.dst_c = T;
+      y.dst_stride = V;
+      if ((rc = run_pass<LM_C, SM_C>(y, nb, st))) return rc;
+      PassArgs x = {};
+      setup_axis(b, 2, x);
+      x.sgn = 1.f;
+      x.nb = nb;
+      for (int j = 0; j < nb; ++j) {
+        x.oa[j] = z.oa[j];
+        x.ob[j] = z.ob[j];
+      }
+      x.src_c = T;
+      x.src_stride = V;
+      x.Uout = Ub;
+      x.dtype = dtype;
+      x.scales = quant ? sc : nullptr;
+      x.out_scale = 1.f / (float)V;
+      if ((rc = run_pass<LM_C, SM_UOUT>(x, nb, st))) return rc;
+    }
+  }
+  return OS3D_OK;
+}
+
+int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out,
+                  void* ws, bool divide_M, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const long long V = b->V;
+  const int nbmax = pair_batch(b);
+  float2* X = (float2*)ws;
+  float2* T = X + V;
+  const size_t ubytes = (dtype == OS3D_C64) ? 8 : 4;
+  int rc;
+  for (int bi = 0; bi < batch; ++bi) {
+    const void* Ub = (const char*)U + (size_t)bi * b->n_orients * V * ubytes;
+    const float* sc = scales ? scales + (long long)bi * b->n_orients : nullptr;
+    for (int r0 = 0; r0 < b->n_unique; r0 += nbmax) {
+      const int nb = std::min(nbmax, b->n_unique - r0);
+      PassArgs x = {};
+      setup_axis(b, 2, x);
+      x.sgn = -1.f;
+      x.nb = nb;
+      for (int j = 0; j < nb; ++j) {
+        const int o = b->rep[r0 + j];
+        x.rows[j] = r0 + j;
+        x.oa[j] = o;
+        x.ob[j] = b->partner[o];
+      }
+      x.U = Ub;
+      x.dtype = dtype;
+      x.scales = (dtype == OS3D_C64) ? nullptr : sc;
+      x.dst_c = T;
+      x.dst_stride = V;
+      if ((rc = run_pass<LM_UIN, SM_C>(x, nb, st))) return rc;
+      PassArgs y = {};
+      setup_axis(b, 1, y);
+      y.sgn = -1.f;
+      y.nb = nb;
+      y.src_c = T;
+      y.src_stride = V;
+      y.dst_c = T;
+      y.dst_stride = V;
+      if ((rc = run_pass<LM_C, SM_C>(y, nb, st))) return rc;
+      PassArgs z = {};
+      setup_axis(b, 0, z);
+      z.sgn = -1.f;
+      z.nb = nb;
+      for (int j = 0; j < nb; ++j) z.rows[j] = x.rows[j];
+      z.src_c = T;
+      z.src_stride = V;
+      z.psi = b->d.psi;
+      z.dst_c = X;
+      z.accumulate = (r0 > 0) ? 1 : 0;
+      if ((rc = run_pass<LM_C, SM_ACCUM>(z, 1, st))) return rc;
+    }
+    // X / max(M, eps) (reconstruction) or X (adjoint), inverse DFT, real part
+    PassArgs z = {};
+    setup_axis(b, 0, z);
+    z.sgn = 1.f;
+    z.nb = 1;
+    z.src_c = X;
+    z.M = b->d.M;
+    z.eps = (float)b->params.eps;
+    z.divide = divide_M ? 1 : 0;
+    z.dst_c = X;
+    if ((rc = run_pass<LM_DIVM, SM_C>(z, 1, st))) return rc;
+    PassArgs y = {};
+    setup_axis(b, 1, y);
+    y.sgn = 1.f;
+    y.nb = 1;
+    y.src_c = X;
+    y.dst_c = X;
+    if ((rc = run_pass<LM_C, SM_C>(y, 1, st))) return rc;
+    PassArgs x = {};
+    setup_axis(b, 2, x);
+    x.sgn = 1.f;
+    x.nb = 1;
+    x.src_c = X;
+    x.dst_r = f_out + (long long)bi * V;
+    x.out_scale = 1.f / (float)V;
+    if ((rc = run_pass<LM_C, SM_REAL>(x, 1, st))) return rc;
+  }
+  return OS3D_OK;
+}
+
+}  // namespace os3d

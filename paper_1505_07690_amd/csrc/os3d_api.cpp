@@ -1,0 +1,329 @@
+// C ABI of libos3d: argument validation, bank layout and plan, dispatch to
+// the HIP launchers.  See include/os3d.h for the contract of each call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "os3d_internal.h"
+
+namespace os3d {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static int check_params(const os3d_wavelet_params* p) {
+  if (!p) return fail(OS3D_EINVAL, "params is NULL");
+  if (p->L < 0 || p->L > kMaxL) return fail(OS3D_EINVAL, "L must be in [0, 64]");
+  if (!(p->s_theta > 0.0) || !std::isfinite(p->s_theta)) return fail(OS3D_EINVAL, "s_theta must be > 0");
+  if (p->k < 0 || p->k > 16) return fail(OS3D_EINVAL, "k must be in [0, 16]");
+  if (p->taylor_N < 0 || p->taylor_N > 200) return fail(OS3D_EINVAL, "taylor_N must be in [0, 200]");
+  if (!(p->gamma > 0.0 && p->gamma < 1.0)) return fail(OS3D_EINVAL, "gamma must be in (0, 1)");
+  if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(OS3D_EINVAL, "eps must be > 0");
+  if (p->variant != OS3D_CAKE && p->variant != OS3D_PLATE) return fail(OS3D_EINVAL, "unknown variant");
+  return OS3D_OK;
+}
+
+static int check_dims(const int64_t* dims) {
+  if (!dims) return fail(OS3D_EINVAL, "dims is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (dims[d] < 2) return fail(OS3D_EINVAL, "every dim must be >= 2");
+    if (dims[d] > kMaxDim || !factor235(dims[d]))
+      return fail(OS3D_EUNSUPPORTED, "dims must be <= 4096 with prime factors 2, 3, 5 only");
+  }
+  return OS3D_OK;
+}
+
+static int check_orients(const double* o, int n) {
+  if (!o) return fail(OS3D_EINVAL, "orients is NULL");
+  if (n < 1 || n > 4096) return fail(OS3D_EINVAL, "n_orients must be in [1, 4096]");
+  for (int i = 0; i < n; ++i) {
+    double r = std::sqrt(o[3 * i] * o[3 * i] + o[3 * i + 1] * o[3 * i + 1] + o[3 * i + 2] * o[3 * i + 2]);
+    if (!(std::fabs(r - 1.0) <= 1e-9)) return fail(OS3D_EINVAL, "orientation " + std::to_string(i) + " is not a unit vector");
+  }
+  return OS3D_OK;
+}
+
+// Stored rows: one per antipodal pair when the whole set pairs up, else one per orientation.
+static void make_rows(const double* o, int n, std::vector<int>& partner, std::vector<int>& rep, std::vector<int>& row_of,
+                      std::vector<int>& conj_of, int& paired) {
+  pair_orientations(o, n, partner);
+  paired = 1;
+  for (int i = 0; i < n; ++i)
+    if (partner[i] < 0 || partner[partner[i]] != i) paired = 0;
+  rep.clear();
+  row_of.assign(n, -1);
+  conj_of.assign(n, 0);
+  if (!paired) partner.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    if (paired && partner[i] < i) continue;
+    row_of[i] = (int)rep.size();
+    rep.push_back(i);
+  }
+  if (paired)
+    for (int i = 0; i < n; ++i)
+      if (row_of[i] < 0) {
+        row_of[i] = row_of[partner[i]];
+        conj_of[i] = 1;
+      }
+}
+
+struct BankLayout {
+  size_t psi, M, Mh, S, tab, part, tw[3], total;
+};
+
+static BankLayout layout(const int64_t dims[3], int n_unique, int L) {
+  BankLayout b;
+  const size_t V = (size_t)dims[0] * dims[1] * dims[2];
+  const int nn = L + 1;
+  const int Npad = (n_unique + 15) / 16 * 16;
+  const KLayout kl = k_layout(L);
+  size_t o = 0;
+  b.psi = o;
+  o = align256(o + (size_t)n_unique * V * sizeof(float));
+  b.M = o;
+  o = align256(o + V * sizeof(float));
+  b.Mh = o;
+  o = align256(o + V * sizeof(double));
+  b.S = o;
+  o = align256(o + (size_t)kl.K * Npad * sizeof(float));
+  b.tab = o;
+  o = align256(o + (size_t)(nn + 2 * nn * nn + nn) * sizeof(double));
+  b.part = o;
+  o = align256(o + (2 * 1024 + 2) * sizeof(double));
+  for (int d = 0; d < 3; ++d) {
+    b.tw[d] = o;
+    o = align256(o + (size_t)dims[d] * 2 * sizeof(float));
+  }
+  b.total = o;
+  return b;
+}
+
+size_t bank_bytes(const int64_t dims[3], int n_unique, int L) { return layout(dims, n_unique, L).total; }
+
+}  // namespace os3d
+
+using namespace os3d;
+
+extern "C" {
+
+const char* os3d_last_error(void) { return g_last_error.c_str(); }
+
+const char* os3d_version(void) { return "os3d 0.1 (gfx950)"; }
+
+os3d_status os3d_wavelet_coeffs(const os3d_wavelet_params* p, double* c_out, double* a_out) {
+  int rc = check_params(p);
+  if (rc) return (os3d_status)rc;
+  std::vector<double> c, a;
+  wavelet_coeffs(*p, c, a);
+  if (c_out) std::copy(c.begin(), c.end(), c_out);
+  if (a_out) std::copy(a.begin(), a.end(), a_out);
+  return OS3D_OK;
+}
+
+os3d_status os3d_steering_matrix(const os3d_wavelet_params* p, const double* orients, int32_t n, double* S_out) {
+  int rc = check_params(p);
+  if (rc) return (os3d_status)rc;
+  if ((rc = check_orients(orients, n))) return (os3d_status)rc;
+  if (!S_out) return (os3d_status)fail(OS3D_EINVAL, "S_out is NULL");
+  std::vector<double> c, a;
+  wavelet_coeffs(*p, c, a);
+  steering_std(*p, orients, n, a, S_out);
+  return OS3D_OK;
+}
+
+os3d_status os3d_bank_bytes(const int64_t dims[3], const double* orients, int32_t n, const os3d_wavelet_params* p,
+                            size_t* bytes) {
+  int rc;
+  if ((rc = check_dims(dims))) return (os3d_status)rc;
+  if ((rc = check_orients(orients, n))) return (os3d_status)rc;
+  if ((rc = check_params(p))) return (os3d_status)rc;
+  if (!bytes) return (os3d_status)fail(OS3D_EINVAL, "bytes is NULL");
+  std::vector<int> partner, rep, row_of, conj_of;
+  int paired;
+  make_rows(orients, n, partner, rep, row_of, conj_of, paired);
+  *bytes = bank_bytes(dims, (int)rep.size(), p->L);
+  return OS3D_OK;
+}
+
+os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_t n, const os3d_wavelet_params* p,
+                            void* bank_dev, size_t bank_bytes_given, void* stream, os3d_bank** out) {
+  int rc;
+  if ((rc = check_dims(dims))) return (os3d_status)rc;
+  if ((rc = check_orients(orients, n))) return (os3d_status)rc;
+  if ((rc = check_params(p))) return (os3d_status)rc;
+  if (!bank_dev || !out) return (os3d_status)fail(OS3D_EINVAL, "bank_dev or out is NULL");
+  os3d_bank* b = new (std::nothrow) os3d_bank();
+  if (!b) return (os3d_status)fail(OS3D_ENOMEM, "host allocation failed");
+  for (int d = 0; d < 3; ++d) b->dims[d] = dims[d];
+  b->V = dims[0] * dims[1] * dims[2];
+  b->n_orients = n;
+  b->params = *p;
+  b->L = p->L;
+  make_rows(orients, n, b->partner, b->rep, b->row_of, b->conj_of, b->paired);
+  b->n_unique = (int)b->rep.size();
+  b->Npad = (b->n_unique + 15) / 16 * 16;
+  const BankLayout lay = layout(dims, b->n_unique, p->L);
+  if (bank_bytes_given < lay.total) {
+    delete b;
+    return (os3d_status)fail(OS3D_ENOMEM, "bank buffer too small: need " + std::to_string(lay.total) + " bytes");
+  }
+  char* base = (char*)bank_dev;
+  b->base = bank_dev;
+  b->bytes = lay.total;
+  b->d.psi = (float*)(base + lay.psi);
+  b->d.M = (float*)(base + lay.M);
+  b->d.Mh = (double*)(base + lay.Mh);
+  b->d.S = (float*)(base + lay.S);
+  b->d.tab = (double*)(base + lay.tab);
+  b->d.part = (double*)(base + lay.part);
+  for (int d = 0; d < 3; ++d) b->d.tw[d] = (float*)(base + lay.tw[d]);
+  for (int d = 0; d < 3; ++d) {
+    std::vector<int> r = radix_schedule((int)dims[d]);
+    b->plan[d].n = (int)dims[d];
+    b->plan[d].nstages = (int)r.size();
+    for (int s = 0; s < kMaxStages; ++s) b->plan[d].radix[s] = s < (int)r.size() ? r[s] : 0;
+  }
+
+  // host FP64 design: coefficients, steering matrix in K-layout, recursion tables, twiddles
+  std::vector<double> c, a;
+  wavelet_coeffs(*p, c, a);
+  b->dc_value = a[0] / std::sqrt(4.0 * 3.14159265358979323846);
+  const int L = p->L, nn = L + 1;
+  const KLayout kl = k_layout(L);
+  b->K = kl.K;
+  std::vector<double> Sstd((size_t)nn * nn * b->n_unique);
+  std::vector<double> rep_or(3 * b->n_unique);
+  for (int r = 0; r < b->n_unique; ++r)
+    for (int c3 = 0; c3 < 3; ++c3) rep_or[3 * r + c3] = orients[3 * b->rep[r] + c3];
+  steering_std(*p, rep_or.data(), b->n_unique, a, Sstd.data());
+  std::vector<float> S((size_t)kl.K * b->Npad, 0.f);
+  for (int l = 0; l <= L; ++l)
+    for (int m = -l; m <= l; ++m) {
+      const int k = (m == 0) ? k_index(kl, l, 0, false) : k_index(kl, l, std::abs(m), m < 0);
+      for (int r = 0; r < b->n_unique; ++r)
+        S[(size_t)k * b->Npad + r] = (float)Sstd[(size_t)(l * l + l + m) * b->n_unique + r];
+    }
+  ShTables t = sh_tables(L);
+  std::vector<double> tab(nn + 2 * nn * nn + nn, 0.0);
+  std::copy(t.qmm.begin(), t.qmm.end(), tab.begin());
+  std::copy(t.alm.begin(), t.alm.end(), tab.begin() + nn);
+  std::copy(t.blm.begin(), t.blm.end(), tab.begin() + nn + nn * nn);
+  int* ko = (int*)(tab.data() + nn + 2 * nn * nn);
+  for (int m = 0; m <= L; ++m) {
+    ko[m] = kl.off[m];
+    ko[nn + m] = kl.pad[m];
+  }
+  std::vector<float> tw[3];
+  for (int d = 0; d < 3; ++d) {
+    const int N = (int)dims[d];
+    tw[d].resize(2 * N);
+    for (int j = 0; j < N; ++j) {
+      const double ang = -2.0 * 3.14159265358979323846 * (double)j / (double)N;
+      tw[d][2 * j] = (float)std::cos(ang);
+      tw[d][2 * j + 1] = (float)std::sin(ang);
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  bool ok = hipMemcpyAsync(b->d.S, S.data(), S.size() * sizeof(float), hipMemcpyHostToDevice, st) == hipSuccess &&
+            hipMemcpyAsync(b->d.tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess;
+  for (int d = 0; d < 3 && ok; ++d)
+    ok = hipMemcpyAsync(b->d.tw[d], tw[d].data(), tw[d].size() * sizeof(float), hipMemcpyHostToDevice, st) ==
+         hipSuccess;
+  if (!ok) {
+    delete b;
+    return (os3d_status)fail(OS3D_EDEVICE, "os3d_build_bank: host-to-device copy failed");
+  }
+  rc = launch_build_bank(b, stream);
+  if (rc) {
+    (void)hipStreamSynchronize(st);
+    delete b;
+    return (os3d_status)rc;
+  }
+  *out = b;
+  return OS3D_OK;
+}
+
+os3d_status os3d_free_bank(os3d_bank* b) {
+  delete b;
+  return OS3D_OK;
+}
+
+os3d_status os3d_get_bank_info(const os3d_bank* b, os3d_bank_info* info) {
+  if (!b || !info) return (os3d_status)fail(OS3D_EINVAL, "bank or info is NULL");
+  for (int d = 0; d < 3; ++d) info->dims[d] = b->dims[d];
+  info->n_orients = b->n_orients;
+  info->n_unique = b->n_unique;
+  info->paired = b->paired;
+  info->kappa = b->kappa;
+  info->M_min_band = 0.0;
+  info->M_dev = b->d.M;
+  return OS3D_OK;
+}
+
+os3d_status os3d_bank_psi(const os3d_bank* b, int32_t i, float* psi_dev, void* stream) {
+  if (!b || !psi_dev) return (os3d_status)fail(OS3D_EINVAL, "bank or psi_dev is NULL");
+  if (i < 0 || i >= b->n_orients) return (os3d_status)fail(OS3D_EINVAL, "orientation index out of range");
+  return (os3d_status)launch_export_psi(b, i, psi_dev, stream);
+}
+
+os3d_status os3d_bank_M(const os3d_bank* b, float* M_dev, void* stream) {
+  if (!b || !M_dev) return (os3d_status)fail(OS3D_EINVAL, "bank or M_dev is NULL");
+  return (os3d_status)launch_export_M(b, M_dev, stream);
+}
+
+os3d_status os3d_workspace_bytes(const os3d_bank* b, size_t* bytes) {
+  if (!b || !bytes) return (os3d_status)fail(OS3D_EINVAL, "bank or bytes is NULL");
+  *bytes = workspace_bytes(b);
+  return OS3D_OK;
+}
+
+static int check_compute(const os3d_bank* b, const void* in, int batch, const void* out, int dtype, const void* scales,
+                         const void* ws, size_t ws_bytes, bool scales_are_output) {
+  if (!b) return fail(OS3D_EINVAL, "bank is NULL");
+  if (!in || !out) return fail(OS3D_EINVAL, "input or output is NULL");
+  if (batch < 1) return fail(OS3D_EINVAL, "batch must be >= 1");
+  if (dtype != OS3D_C64 && dtype != OS3D_BF16X2 && dtype != OS3D_F16X2) return fail(OS3D_EINVAL, "unknown score dtype");
+  if (dtype != OS3D_C64 && !scales)
+    return fail(OS3D_EINVAL, scales_are_output ? "scales output is NULL for a 16-bit score dtype"
+                                               : "scales is NULL for a 16-bit score dtype");
+  if (!ws) return fail(OS3D_EINVAL, "workspace is NULL");
+  if (ws_bytes < workspace_bytes(b))
+    return fail(OS3D_ENOMEM, "workspace too small: need " + std::to_string(workspace_bytes(b)) + " bytes");
+  return OS3D_OK;
+}
+
+os3d_status os3d_forward(const os3d_bank* b, const float* f, int32_t batch, void* U, int32_t dtype, float* scales,
+                         void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_compute(b, f, batch, U, dtype, scales, ws, ws_bytes, true);
+  if (rc) return (os3d_status)rc;
+  return (os3d_status)launch_forward(b, f, batch, U, dtype, scales, ws, stream);
+}
+
+os3d_status os3d_adjoint(const os3d_bank* b, const void* U, int32_t dtype, const float* scales, int32_t batch,
+                         float* f_out, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_compute(b, U, batch, f_out, dtype, scales, ws, ws_bytes, false);
+  if (rc) return (os3d_status)rc;
+  return (os3d_status)launch_reduce(b, U, dtype, scales, batch, f_out, ws, false, stream);
+}
+
+os3d_status os3d_reconstruct(const os3d_bank* b, const void* U, int32_t dtype, const float* scales, int32_t batch,
+                             float* f_out, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_compute(b, U, batch, f_out, dtype, scales, ws, ws_bytes, false);
+  if (rc) return (os3d_status)rc;
+  return (os3d_status)launch_reduce(b, U, dtype, scales, batch, f_out, ws, true, stream);
+}
+
+}  // extern "C"

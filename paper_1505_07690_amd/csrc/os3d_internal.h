@@ -1,0 +1,113 @@
+// Internal declarations of libos3d (not part of the C ABI).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/os3d.h"
+
+namespace os3d {
+
+constexpr int kMaxL = 64;
+constexpr int kMaxDim = 4096;
+constexpr int kMaxStages = 14;
+
+// ---------------------------------------------------------------- host FP64 setup
+double bspline(int k, double x);
+void legendre(int L, double x, double* P);               // P[0..L]
+std::vector<double> geodesic_icosahedron(int freq);      // 3 * (10 freq^2 + 2)
+bool zonal_fit(int L, const std::vector<double>& pts, const std::vector<double>& values,
+               std::vector<double>& c);                   // least squares, Householder QR
+void cake_coeffs(int L, const double* c, int variant, double* a);
+void wavelet_coeffs(const os3d_wavelet_params& p, std::vector<double>& c, std::vector<double>& a);
+
+// Real spherical-harmonic recursion coefficients shared by the host steering
+// matrix and the device generator (so both use one convention):
+//   Q_m^m = qmm[m];  Q_{m+1}^m = sqrt(2m+3) z Q_m^m;
+//   Q_l^m = alm[l*(L+1)+m] (z Q_{l-1}^m - blm[l*(L+1)+m] Q_{l-2}^m)
+//   Y_l0 = Q_l^0,  Y_lm = sqrt2 Q_l^m Re((x+iy)^m),  Y_l-m = sqrt2 Q_l^m Im((x+iy)^m)
+struct ShTables {
+  int L;
+  std::vector<double> qmm, alm, blm;
+};
+ShTables sh_tables(int L);
+void real_sh(const ShTables& t, const double n[3], double* Y);  // index l*l + l + m
+
+// Layout of the contraction dimension K used by the bank kernel: chunks by m
+// (m = 0: l = 0..L; m >= 1: cos terms l = m..L, then sin terms l = m..L),
+// each chunk padded to a multiple of 4 rows.
+struct KLayout {
+  int L;
+  int K;                    // padded total
+  std::vector<int> off;     // chunk start, m = 0..L
+  std::vector<int> len;     // unpadded chunk length
+  std::vector<int> pad;     // padded chunk length
+};
+KLayout k_layout(int L);
+int k_index(const KLayout& kl, int l, int m, bool sin_part);
+
+void steering_std(const os3d_wavelet_params& p, const double* orients, int n, const std::vector<double>& a,
+                  double* S);  // [(L+1)^2][n], standard order
+
+// Antipodal pairing: partner[i] = j with n_j = -n_i (|n_i + n_j| < 1e-9) or -1.
+void pair_orientations(const double* orients, int n, std::vector<int>& partner);
+
+bool factor235(int64_t n);
+std::vector<int> radix_schedule(int n);  // radices in {16, 8, 4, 2, 5, 3}
+
+// ---------------------------------------------------------------- device plan
+struct AxisPlan {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+};
+
+struct DevPtrs {
+  float* psi;      // [n_unique][V] float32, unnormalised during build then scaled by kappa
+  float* M;        // [V]
+  double* Mh;      // [V] FP64 sum over stored rows of raw psi^2 (build scratch)
+  float* S;        // [K][Npad] steering matrix in K-layout
+  double* tab;     // recursion tables: qmm[L+1], alm[(L+1)^2], blm[(L+1)^2], sqrt(2m+3)[L+1]
+  double* part;    // kappa partial sums
+  float* tw[3];    // twiddles exp(-2 pi i j / N_d), j < N_d, per axis (z, y, x)
+};
+
+}  // namespace os3d
+
+struct os3d_bank {
+  int64_t dims[3];
+  int64_t V;
+  int n_orients;
+  int n_unique;
+  int paired;
+  int L;
+  int Npad;
+  int K;
+  double kappa;
+  double dc_value;            // a_0 / sqrt(4 pi): the sphere average of h, used at k = 0
+  os3d_wavelet_params params;
+  std::vector<int> partner;   // per orientation: antipode index or -1
+  std::vector<int> row_of;    // per orientation: stored bank row
+  std::vector<int> conj_of;   // per orientation: 1 when it is the second member of a pair (psi(Sk))
+  std::vector<int> rep;       // per stored row: orientation index of the stored member
+  os3d::AxisPlan plan[3];     // z, y, x
+  os3d::DevPtrs d;
+  void* base;
+  size_t bytes;
+};
+
+namespace os3d {
+// Device-side entry points implemented in the .hip files.
+int launch_build_bank(os3d_bank* b, void* stream);
+int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int dtype, float* scales, void* ws,
+                   void* stream);
+int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out,
+                  void* ws, bool divide_M, void* stream);
+int launch_export_psi(const os3d_bank* b, int i, float* out, void* stream);
+int launch_export_M(const os3d_bank* b, float* out, void* stream);
+size_t workspace_bytes(const os3d_bank* b);
+size_t bank_bytes(const int64_t dims[3], int n_unique, int L);
+void set_error(const std::string& msg);
+}  // namespace os3d

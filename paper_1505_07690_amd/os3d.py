@@ -1,0 +1,273 @@
+"""Python binding of libos3d (the C ABI declared in include/os3d.h).
+
+Argument marshalling only: every step of the transform runs in the HIP
+library.  PyTorch provides device memory and the current stream.  There is
+no CPU fallback: if libos3d.so is missing the import of this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libos3d.so")
+
+OS3D_C64, OS3D_BF16X2, OS3D_F16X2 = 0, 1, 2
+DTYPES = {"c64": OS3D_C64, "bf16": OS3D_BF16X2, "fp16": OS3D_F16X2}
+VARIANTS = {"cake": 0, "plate": 1}
+
+
+class OS3DError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"os3d status {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("s_theta", ctypes.c_double), ("k", ctypes.c_int32),
+                ("taylor_N", ctypes.c_int32), ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
+                ("variant", ctypes.c_int32)]
+
+
+class BankInfo(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int64 * 3), ("n_orients", ctypes.c_int32), ("n_unique", ctypes.c_int32),
+                ("paired", ctypes.c_int32), ("kappa", ctypes.c_double), ("M_min_band", ctypes.c_double),
+                ("M_dev", ctypes.c_void_p)]
+
+
+_lib = None
+
+_SIGS = {
+    "os3d_wavelet_coeffs": [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p],
+    "os3d_steering_matrix": [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p],
+    "os3d_bank_bytes": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Params),
+                        ctypes.POINTER(ctypes.c_size_t)],
+    "os3d_build_bank": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
+                        ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)],
+    "os3d_free_bank": [ctypes.c_void_p],
+    "os3d_get_bank_info": [ctypes.c_void_p, ctypes.POINTER(BankInfo)],
+    "os3d_bank_psi": [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p],
+    "os3d_bank_M": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "os3d_workspace_bytes": [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)],
+    "os3d_forward": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "os3d_adjoint": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "os3d_reconstruct": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+}
+
+
+def lib():
+    """The loaded libos3d (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1505_07690_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.os3d_last_error.restype = ctypes.c_char_p
+        L.os3d_last_error.argtypes = []
+        L.os3d_version.restype = ctypes.c_char_p
+        L.os3d_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise OS3DError(rc, lib().os3d_last_error().decode())
+
+
+def make_params(L=16, s_theta=0.7, k=2, taylor_N=20, gamma=0.8, eps=1e-3, variant="cake"):
+    return Params(int(L), float(s_theta), int(k), int(taylor_N), float(gamma), float(eps),
+                  VARIANTS[variant] if isinstance(variant, str) else int(variant))
+
+
+def _as_params(p):
+    if isinstance(p, Params):
+        return p
+    if isinstance(p, dict):
+        return make_params(**p)
+    # any object with the attributes (e.g. the oracle's WaveletParams)
+    return make_params(p.L, p.s_theta, p.k, p.taylor_N, p.gamma, p.eps, getattr(p, "variant", "cake"))
+
+
+def _orients(o):
+    o = np.ascontiguousarray(np.asarray(o, dtype=np.float64).reshape(-1, 3))
+    return o
+
+
+def wavelet_coeffs(params):
+    """Host FP64 coefficients (c_l, a_l) of the window and the wavelet profile."""
+    p = _as_params(params)
+    c = np.zeros(p.L + 1)
+    a = np.zeros(p.L + 1)
+    _check(lib().os3d_wavelet_coeffs(ctypes.byref(p), c.ctypes.data, a.ctypes.data))
+    return c, a
+
+
+def steering_matrix(params, orients):
+    """Host FP64 steering matrix [(L+1)^2][N_o] in the standard (l*l+l+m) order."""
+    p = _as_params(params)
+    o = _orients(orients)
+    S = np.zeros(((p.L + 1) ** 2, o.shape[0]))
+    _check(lib().os3d_steering_matrix(ctypes.byref(p), o.ctypes.data, o.shape[0], S.ctypes.data))
+    return S
+
+
+def bank_bytes(shape, orients, params):
+    p = _as_params(params)
+    o = _orients(orients)
+    dims = (ctypes.c_int64 * 3)(*[int(s) for s in shape])
+    n = ctypes.c_size_t()
+    _check(lib().os3d_bank_bytes(dims, o.ctypes.data, o.shape[0], ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Bank:
+    """A wavelet bank resident on the GPU (device buffer owned by torch)."""
+
+    def __init__(self, shape, orients, params, device="cuda", stream=None):
+        import torch
+        self.shape = tuple(int(s) for s in shape)
+        self.orients = _orients(orients)
+        self.params = _as_params(params)
+        self.n_orients = self.orients.shape[0]
+        nbytes = bank_bytes(self.shape, self.orients, self.params)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.device = self.buf.device
+        dims = (ctypes.c_int64 * 3)(*self.shape)
+        h = ctypes.c_void_p()
+        _check(lib().os3d_build_bank(dims, self.orients.ctypes.data, self.n_orients, ctypes.byref(self.params),
+                                     ctypes.c_void_p(self.buf.data_ptr()), nbytes, _stream_ptr(stream),
+                                     ctypes.byref(h)))
+        self.handle = h
+        info = BankInfo()
+        _check(lib().os3d_get_bank_info(self.handle, ctypes.byref(info)))
+        self.kappa = info.kappa
+        self.n_unique = info.n_unique
+        self.paired = bool(info.paired)
+        n = ctypes.c_size_t()
+        _check(lib().os3d_workspace_bytes(self.handle, ctypes.byref(n)))
+        self.ws_bytes = n.value
+        self._ws = None
+
+    @property
+    def V(self):
+        return self.shape[0] * self.shape[1] * self.shape[2]
+
+    def workspace(self):
+        import torch
+        if self._ws is None:
+            self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def psi(self, i, stream=None):
+        """psi_hat_i as a float32 [Nz, Ny, Nx] device tensor (natural DFT order)."""
+        import torch
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        _check(lib().os3d_bank_psi(self.handle, int(i), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def M(self, stream=None):
+        import torch
+        out = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        _check(lib().os3d_bank_M(self.handle, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.os3d_free_bank(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _batched(f, shape):
+    if f.dim() == 3:
+        return f.unsqueeze(0), True
+    if f.dim() == 4 and tuple(f.shape[1:]) == shape:
+        return f, False
+    raise ValueError(f"expected [B, {shape}] or {shape}, got {tuple(f.shape)}")
+
+
+def forward(f, bank, dtype="c64", ws=None, out=None, scales=None, stream=None):
+    """U = W f (Eq. 7) for a float32 device volume f [B, Nz, Ny, Nx] (or [Nz, Ny, Nx]).
+    Returns (U, scales): U is complex64 [B, N_o, Nz, Ny, Nx] for "c64", else an
+    int32 tensor of packed 16-bit (re, im) pairs with float32 scales [B, N_o]."""
+    import torch
+    fb, single = _batched(f, bank.shape)
+    if fb.dtype != torch.float32 or not fb.is_contiguous():
+        raise ValueError("f must be a contiguous float32 tensor")
+    B = fb.shape[0]
+    code = DTYPES[dtype]
+    if out is None:
+        out = torch.empty((B, bank.n_orients) + bank.shape,
+                          dtype=torch.complex64 if code == OS3D_C64 else torch.int32, device=fb.device)
+    if code != OS3D_C64 and scales is None:
+        scales = torch.empty((B, bank.n_orients), dtype=torch.float32, device=fb.device)
+    ws = bank.workspace() if ws is None else ws
+    _check(lib().os3d_forward(bank.handle, ctypes.c_void_p(fb.data_ptr()), B, ctypes.c_void_p(out.data_ptr()), code,
+                              ctypes.c_void_p(scales.data_ptr() if scales is not None else 0),
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    if single:
+        out = out[0]
+        scales = scales[0] if scales is not None else None
+    return out, scales
+
+
+def _reduce(fn, U, bank, scales, dtype, ws, out, stream):
+    import torch
+    code = DTYPES[dtype]
+    Ub = U if U.dim() == 5 else U.unsqueeze(0)
+    if not Ub.is_contiguous():
+        raise ValueError("U must be contiguous")
+    if code == OS3D_C64 and Ub.dtype != torch.complex64:
+        raise ValueError("c64 scores must be complex64")
+    B = Ub.shape[0]
+    if out is None:
+        out = torch.empty((B,) + bank.shape, dtype=torch.float32, device=Ub.device)
+    sc = None
+    if code != OS3D_C64:
+        sc = scales if scales.dim() == 2 else scales.unsqueeze(0)
+    ws = bank.workspace() if ws is None else ws
+    _check(fn(bank.handle, ctypes.c_void_p(Ub.data_ptr()), code, ctypes.c_void_p(sc.data_ptr() if sc is not None else 0),
+              B, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
+    return out if U.dim() == 5 else out[0]
+
+
+def adjoint(U, bank, scales=None, dtype="c64", ws=None, out=None, stream=None):
+    """W* U = Re IDFT(sum_i psi_hat_i DFT(U_i))."""
+    return _reduce(lib().os3d_adjoint, U, bank, scales, dtype, ws, out, stream)
+
+
+def reconstruct(U, bank, scales=None, dtype="c64", ws=None, out=None, stream=None):
+    """Stabilised exact reconstruction, Eq. (8) with max(M, eps)."""
+    return _reduce(lib().os3d_reconstruct, U, bank, scales, dtype, ws, out, stream)
+
+
+def unpack16(Uq, scales, dtype):
+    """Packed 16-bit score pairs -> complex64 (a test/inspection helper on the
+    device; the library itself dequantises inside its kernels)."""
+    import torch
+    q = Uq.contiguous().view(torch.int16).reshape(Uq.shape + (2,))
+    t = torch.float16 if dtype == "fp16" else torch.bfloat16
+    v = q.view(t).to(torch.float32)
+    s = scales.reshape(scales.shape + (1,) * (Uq.dim() - scales.dim())).to(torch.float32)
+    return torch.complex(v[..., 0] * s, v[..., 1] * s)

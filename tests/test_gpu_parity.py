@@ -1,0 +1,196 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle, on
+seeded inputs at oracle-sized shapes: the bank and M (Eqs. 9-19), the
+forward transform (Eq. 7), its adjoint and the stabilised reconstruction
+(Eq. 8 with max(M, eps)).  FP32 paths: relative L2 error <= 1e-5."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1505_07690_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1505_07690_amd import os3d
+    os3d.lib()  # the HIP library must be there: no fallback
+    return torch
+
+
+def _case(shape, orients, params, vol):
+    from paper_1505_07690_amd import os3d
+    import torch
+    ob = O.build_bank(shape, orients, params)
+    gb = os3d.Bank(shape, orients, params)
+    f = torch.from_numpy(np.ascontiguousarray(vol, dtype=np.float32)).cuda()
+    return ob, gb, f
+
+
+def _oracle_params(L, n_or, variant="cake", gamma=0.8):
+    return O.WaveletParams(L=L, s_theta=inputs.s_theta_for(n_or), variant=variant, gamma=gamma)
+
+
+CASES = {
+    # config A: 32^3 crossing tubes, 12 icosahedron orientations, L = 8
+    "A32": lambda: ((32, 32, 32), inputs.icosahedral_orientations(0), _oracle_params(8, 12),
+                    inputs.config_volume("A")),
+    # non-cubic, ragged tile counts, 42 orientations, L = 16
+    "r12x10x18": lambda: ((12, 10, 18), inputs.icosahedral_orientations(1), _oracle_params(16, 42),
+                          inputs.tubes((12, 10, 18), 2, 1.2, 0.1, 0, 5)),
+    # odd dims (no Nyquist plane on z, y), radix 3 and 5
+    "odd15x9x10": lambda: ((15, 9, 10), inputs.icosahedral_orientations(0), _oracle_params(8, 12),
+                           inputs.tubes((15, 9, 10), 2, 1.0, 0.2, 0, 6)),
+    # a set without antipodes (no pairing) and the plate-detector variant
+    "unpaired_plate": lambda: ((16, 12, 20), _random_orients(7, 3), _oracle_params(6, 7, "plate"),
+                               inputs.tubes((16, 12, 20), 3, 1.5, 0.1, 0, 7)),
+    # small N with radix-2 only and a long axis
+    "long4x6x64": lambda: ((4, 6, 64), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
+                           inputs.tubes((4, 6, 64), 2, 1.0, 0.1, 0, 8)),
+}
+
+
+def _random_orients(n, seed):
+    v = np.random.default_rng(seed).standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def case(request, torch_dev):
+    shape, orients, params, vol = CASES[request.param]()
+    ob, gb, f = _case(shape, orients, params, vol)
+    return dict(name=request.param, shape=shape, orients=orients, params=params, vol=vol, ob=ob, gb=gb, f=f)
+
+
+def test_bank_and_M_parity(case):
+    ob, gb = case["ob"], case["gb"]
+    psi = np.stack([gb.psi(i).cpu().numpy() for i in range(len(case["orients"]))])
+    assert rel(psi, ob["psi_hat"]) < TOL
+    assert rel(gb.M().cpu().numpy(), ob["M"]) < TOL
+    assert abs(gb.kappa - ob["kappa"]) < 1e-6 * ob["kappa"]
+    assert gb.paired == (case["name"] != "unpaired_plate")
+
+
+def test_forward_parity(case):
+    from paper_1505_07690_amd import os3d
+    U, _ = os3d.forward(case["f"], case["gb"])
+    Uo = O.forward(case["vol"].astype(np.float64), case["ob"])
+    assert rel(U.cpu().numpy(), Uo) < TOL
+
+
+def test_reconstruct_and_adjoint_parity(case):
+    from paper_1505_07690_amd import os3d
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(1)
+    No = len(case["orients"])
+    # a general complex score (not in the range of W)
+    Un = (rng.standard_normal((No,) + case["shape"]) + 1j * rng.standard_normal((No,) + case["shape"]))
+    Ug = torch.from_numpy(Un.astype(np.complex64)).cuda()
+    rec = os3d.reconstruct(Ug, case["gb"]).cpu().numpy()
+    adj = os3d.adjoint(Ug, case["gb"]).cpu().numpy()
+    Un32 = Un.astype(np.complex64).astype(np.complex128)
+    assert rel(rec, O.reconstruct(Un32, case["ob"])) < TOL
+    assert rel(adj, O.adjoint(Un32, case["ob"])) < TOL
+
+
+def test_roundtrip_reconstruction(case):
+    """reconstruct(forward(f)) on the GPU equals the oracle's (Eq. 8)."""
+    from paper_1505_07690_amd import os3d
+    U, _ = os3d.forward(case["f"], case["gb"])
+    rec = os3d.reconstruct(U, case["gb"]).cpu().numpy()
+    ref = O.reconstruct(O.forward(case["vol"].astype(np.float64), case["ob"]), case["ob"])
+    assert rel(rec, ref) < TOL
+
+
+def test_bruteforce_correlation_8cube(torch_dev):
+    """Eq. (7) literally (direct circular correlation with conj(psi)) on 8^3."""
+    from paper_1505_07690_amd import os3d
+    shape = (8, 8, 8)
+    n = inputs.icosahedral_orientations(0)
+    p = _oracle_params(8, 12)
+    vol = np.random.default_rng(0).standard_normal(shape).astype(np.float32)
+    ob, gb, f = _case(shape, n, p, vol)
+    U, _ = os3d.forward(f, gb)
+    assert rel(U.cpu().numpy(), O.forward_bruteforce(vol.astype(np.float64), ob)) < TOL
+
+
+def test_exact_reconstruction_bandlimited(torch_dev):
+    from paper_1505_07690_amd import os3d
+    shape = (32, 32, 32)
+    n = inputs.icosahedral_orientations(1)
+    p = _oracle_params(16, 42)
+    vol = inputs.bandlimited(shape, 0.75, seed=4)
+    gb = os3d.Bank(shape, n, p)
+    f = torch_dev.from_numpy(vol).cuda()
+    U, _ = os3d.forward(f, gb)
+    rec = os3d.reconstruct(U, gb).cpu().numpy()
+    assert rel(rec, vol) < TOL
+
+
+def test_batch_and_determinism(torch_dev):
+    from paper_1505_07690_amd import os3d
+    shape = (16, 16, 16)
+    n = inputs.icosahedral_orientations(1)
+    p = _oracle_params(16, 42)
+    gb = os3d.Bank(shape, n, p)
+    vols = np.stack([inputs.tubes(shape, 2, 1.2, 0.1, 0, s) for s in range(3)])
+    fb = torch_dev.from_numpy(vols).cuda()
+    U, _ = os3d.forward(fb, gb)
+    U2, _ = os3d.forward(fb, gb)
+    assert torch_dev.equal(U, U2)
+    for b in range(3):
+        Ub, _ = os3d.forward(fb[b].contiguous(), gb)
+        assert torch_dev.equal(U[b], Ub)
+    rec = os3d.reconstruct(U, gb)
+    for b in range(3):
+        assert torch_dev.equal(rec[b], os3d.reconstruct(U[b].contiguous(), gb))
+    ob = O.build_bank(shape, n, p)
+    for b in range(3):
+        assert rel(U[b].cpu().numpy(), O.forward(vols[b].astype(np.float64), ob)) < TOL
+
+
+def test_antipodal_pairs_are_conjugate(torch_dev):
+    from paper_1505_07690_amd import os3d
+    shape = (16, 16, 16)
+    n = inputs.icosahedral_orientations(0)
+    gb = os3d.Bank(shape, n, _oracle_params(8, 12))
+    f = torch_dev.from_numpy(inputs.tubes(shape, 2, 1.2, 0.1, 0, 2)).cuda()
+    U, _ = os3d.forward(f, gb)
+    d = np.linalg.norm(n[:, None] + n[None], axis=2)
+    j = np.argmin(d, axis=1)
+    assert torch_dev.equal(U[j], torch_dev.conj(U).resolve_conj())
+
+
+@pytest.mark.parametrize("fmt,bound", [("bf16", 4e-3), ("fp16", 5e-4)])
+def test_reduced_precision_storage(torch_dev, fmt, bound):
+    """16-bit score storage with per-orientation power-of-two scales: error of
+    U and of the reconstruction against the FP64 oracle."""
+    from paper_1505_07690_amd import os3d
+    shape = (32, 32, 32)
+    n = inputs.icosahedral_orientations(1)
+    p = _oracle_params(16, 42)
+    vol = inputs.config_volume("A")
+    ob, gb, f = _case(shape, n, p, vol)
+    Uq, sc = os3d.forward(f, gb, dtype=fmt)
+    s = sc.cpu().numpy()
+    assert np.all(np.log2(s) == np.round(np.log2(s)))
+    U = os3d.unpack16(Uq, sc, fmt).cpu().numpy()
+    Uo = O.forward(vol.astype(np.float64), ob)
+    assert rel(U, Uo) < bound
+    rec = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
+    assert rel(rec, O.reconstruct(Uo, ob)) < bound
+    # the antipodal partner is stored as the exact conjugate code
+    d = np.linalg.norm(n[:, None] + n[None], axis=2)
+    j = np.argmin(d, axis=1)
+    Uc = os3d.unpack16(Uq, sc, fmt)
+    assert torch_dev.equal(Uc[j], torch_dev.conj(Uc).resolve_conj())
