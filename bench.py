@@ -1,0 +1,242 @@
+#!/usr/bin/env python
+"""Throughput of the invertible 3D orientation-score transform on one MI355X.
+
+One step = one forward transform (Eq. 7) plus one stabilised reconstruction
+(Eq. 8 with max(M, eps)) of one synthetic crossing-tube volume, through the
+os3d C ABI, with the volume, the bank, the scores and the workspace resident
+in HBM.  The default workload is 256^3 voxels x 162 orientations (twice
+subdivided icosahedron), L = 24, scores stored as complex64.
+
+Prints one JSON line: voxel-orientations per second, per-step p50/p99, the
+roofline of the dominant kernel (per-kernel HIP events recorded by the
+library on its launch stream over the timed region) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload C] [--dtype c64]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_MATRIX_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+
+WORKLOADS = {
+    # name: (config key of the volume recipe, human label)
+    "C": "256^3 crossing tubes (40 tubes, sigma U[1,4], noise 0.3, seed 2), N_o=162, L=24",
+    "B": "128^3 crossing tubes (12 tubes, 5 forced crossings, noise 0.2, seed 1), N_o=42, L=16",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default="c64", choices=["c64", "bf16", "fp16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-orients", type=int, default=4, help="orientations in the oracle's timed sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_source_digest():
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(os.path.join(ROOT, "paper_1505_07690_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1505_07690_amd", "csrc", fn), "rb") as f:
+            h.update(fn.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, digest):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when it is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_digest") != digest:
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(workload, n_sample):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload:
+    the same volume, n_sample orientations of the same set (bank built
+    untimed), timed forward + reconstruct."""
+    import numpy as np
+
+    import oracle as O
+    from paper_1505_07690_amd import inputs
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    c = inputs.CONFIGS[workload]
+    n = inputs.icosahedral_orientations(c["level"])
+    # one member of each of the first n_sample/2 antipodal pairs, plus its antipode
+    d = np.linalg.norm(n[:, None] + n[None], axis=2)
+    partner = np.argmin(d, axis=1)
+    pick = []
+    for i in range(len(n)):
+        if len(pick) >= n_sample:
+            break
+        if i not in pick and partner[i] not in pick:
+            pick += [i, int(partner[i])]
+    sub = n[pick[:n_sample]]
+    p = O.WaveletParams(L=c["L"], s_theta=inputs.s_theta_for(len(n)))
+    vol = inputs.config_volume(workload).astype(np.float64)
+    bank = O.build_bank(c["shape"], sub, p)
+    t0 = time.perf_counter()
+    U = O.forward(vol, bank)
+    O.reconstruct(U, bank)
+    dt = time.perf_counter() - t0
+    V = int(np.prod(c["shape"]))
+    return {"value": len(sub) * V / dt, "unit": "voxel-orientations/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(sub)} of {len(n)} orientations ({len(sub) // 2} antipodal pairs) of the same "
+                      f"{'x'.join(map(str, c['shape']))} volume, forward + reconstruct in FP64 numpy "
+                      f"(DFT matrices per axis, BLAS threads={threads}); bank built untimed; the sample's own "
+                      f"DFT of f and final inverse DFT are included, so the rate is a lower bound; "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        sys.stderr.write("bench.py measures one GPU only: the transform here has no multi-GPU path; "
+                         "run it with --gpus 1\n")
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_1505_07690_amd import inputs, os3d
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        n = 1 << 28  # 1 GiB of float32
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n}))
+        return
+
+    c = inputs.CONFIGS[args.workload]
+    shape = c["shape"]
+    orients = inputs.icosahedral_orientations(c["level"])
+    No = len(orients)
+    V = int(np.prod(shape))
+    p = O.WaveletParams(L=c["L"], s_theta=inputs.s_theta_for(No))
+    vol = inputs.config_volume(args.workload)
+    print(f"[bench] workload {args.workload}: {WORKLOADS[args.workload]}; dtype {args.dtype}", file=sys.stderr,
+          flush=True)
+
+    os3d.profile_enable(True)
+    bank = os3d.Bank(shape, orients, p)
+    prof_bank = os3d.profile_read()
+    os3d.profile_enable(False)
+    bank_ms, bank_flops = 0.0, 0.0
+    if "bank_synth_mfma" in prof_bank:
+        _, bank_ms, _, bank_flops = prof_bank["bank_synth_mfma"]
+
+    f = torch.from_numpy(vol).to(dev)
+    is16 = args.dtype != "c64"
+    U = torch.empty((1, No) + shape, dtype=torch.int32 if is16 else torch.complex64, device=dev)
+    scales = torch.empty((1, No), dtype=torch.float32, device=dev) if is16 else None
+    rec = torch.empty((1,) + shape, dtype=torch.float32, device=dev)
+    ws = bank.workspace()
+    fb = f.unsqueeze(0)
+
+    def step():
+        os3d.forward(fb, bank, dtype=args.dtype, ws=ws, out=U, scales=scales)
+        os3d.reconstruct(U, bank, scales=scales, dtype=args.dtype, ws=ws, out=rec)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    os3d.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(args.steps):
+        step()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = os3d.profile_read()
+    os3d.profile_enable(False)
+    per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    total_ms = sum(per_step)
+    ms_per_step = total_ms / args.steps
+    value = V * No * args.steps / (total_ms / 1e3)
+
+    # dominant kernel: largest summed time over the timed region
+    kname = max(prof, key=lambda k: prof[k][1])
+    launches, kms, kbytes, _ = prof[kname]
+    avg_ms = kms / launches
+    bytes_per_launch = kbytes / launches
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    digest = kernel_source_digest()
+    traffic = load_traffic(kname, digest)
+    s_u = 4 if is16 else 8
+    step_bytes = V * No * 2 * s_u + 8 * V
+    breakdown = {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 4), "share": round(v[1] / sum(x[1] for x in prof.values()), 4),
+                     "alg_bytes_per_launch": v[2] / v[0]} for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+
+    out = {
+        "metric": "voxel-orientations/sec forward+reconstruct, %HBM roofline; p50/p99 latency",
+        "value": value,
+        "unit": "voxel-orientations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "p50_ms": float(np.percentile(per_step, 50)),
+        "p99_ms": float(np.percentile(per_step, 99)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if not is16 else f"f32 compute, {args.dtype} score storage",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "shape": list(shape), "n_orients": No, "L": c["L"],
+                   "score_dtype": args.dtype, "batch": 1},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_per_launch},
+        "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBs": step_bytes / (ms_per_step / 1e3) / 1e9,
+                          "frac": step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "bank_build": {"synth_ms": bank_ms, "alg_tflops": bank_flops / (bank_ms / 1e3) / 1e12 if bank_ms else None,
+                       "mfma_fp32_frac": bank_flops / (bank_ms / 1e3) / 1e12 / FP32_MATRIX_TFLOPS if bank_ms else None},
+        "kernels": breakdown,
+        "wall_s_timed": wall,
+        "source_digest": digest,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_orients)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,24 @@ os3d_status os3d_adjoint(const os3d_bank* bank, const void* U, int32_t dtype, co
 os3d_status os3d_reconstruct(const os3d_bank* bank, const void* U, int32_t dtype, const float* scales,
                              int32_t batch, float* f_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Per-kernel timing (not a method step: measurement support).  While
+ * enabled, every launch of the transform's kernels is bracketed by two HIP
+ * events recorded on its launch stream, and the algorithmic bytes that launch
+ * must move are recorded with it (scores written or read: orientations x V x
+ * bytes per score; the real input and output volumes: 4 V).  Enabling or
+ * disabling clears the records.  Not thread-safe; host memory only. */
+os3d_status os3d_profile_enable(int32_t on);
+
+/* Number of kernel slots that os3d_profile_get reports. */
+os3d_status os3d_profile_count(int32_t* n_kernels);
+
+/* Kernel slot idx: its name (static string), number of recorded launches,
+ * summed event time in ms (waits for the recorded events), summed
+ * algorithmic bytes and summed algorithmic flops (the bank contraction:
+ * 2 V (L+1)^2 rows). */
+os3d_status os3d_profile_get(int32_t idx, const char** name, int64_t* launches, double* total_ms,
+                             double* alg_bytes, double* alg_flops);
+
 /* Message of the calling thread's last non-OK status ("" if none). */
 const char* os3d_last_error(void);
 

@@ -323,7 +323,10 @@ int launch_build_bank(os3d_bank* b, void* stream) {
     set_error("k_bank_synth: cannot reserve LDS");
     return OS3D_EDEVICE;
   }
+  void* tok = prof_start(st);
   hipLaunchKernelGGL(k_bank_synth, dim3((unsigned)nblk), dim3(256), lds, st, a);
+  // algorithmic work of the contraction: 2 V (L+1)^2 n_rows flops
+  prof_stop(tok, st, PROF_BANK, 0.0, 2.0 * (double)b->V * (double)(nn * nn) * (double)b->n_unique);
   int rc = check_launch("k_bank_synth");
   if (rc) return rc;
   const int nparts = 1024;

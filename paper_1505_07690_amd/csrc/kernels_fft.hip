@@ -112,6 +112,59 @@ __device__ __forceinline__ void store_score(void* U, int dtype, long long i, flo
   ((unsigned int*)U)[i] = q;
 }
 
+// Fused first-pass load of element g (line position) for pair slot j.
+template <int LM>
+__device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long g, float& asum) {
+  if constexpr (LM == LM_REAL) {
+    return make_float2(a.src_r[g], 0.f);
+  } else if constexpr (LM == LM_C) {
+    return a.src_c[j * a.src_stride + g];
+  } else if constexpr (LM == LM_MULBANK) {
+    const float p = a.psi[(long long)a.rows[j] * a.V + g];
+    const float2 v = cscale(a.src_c[g], p);
+    asum += sqrtf(v.x * v.x + v.y * v.y);
+    return v;
+  } else if constexpr (LM == LM_UIN) {
+    const int ia = a.oa[j], ib = a.ob[j];
+    const float sa = a.scales ? a.scales[ia] : 1.f;
+    float2 v = load_score(a.U, a.dtype, (long long)ia * a.V + g, sa);
+    if (ib >= 0) {
+      const float sb = a.scales ? a.scales[ib] : 1.f;
+      v = cadd(v, cconj(load_score(a.U, a.dtype, (long long)ib * a.V + g, sb)));
+    }
+    return v;
+  } else {  // LM_DIVM
+    float2 v = a.src_c[g];
+    if (a.divide) v = cscale(v, 1.f / fmaxf(a.M[g], a.eps));
+    return v;
+  }
+}
+
+// Fused last-pass store of element g for pair slot j (SM_ACCUM adds into acc).
+template <int SM>
+__device__ __forceinline__ void store_elem(const PassArgs& a, int j, long long g, float2 v, float2& acc) {
+  if constexpr (SM == SM_C) {
+    a.dst_c[j * a.dst_stride + g] = v;
+  } else if constexpr (SM == SM_UOUT) {
+    const float2 u = cscale(v, a.out_scale);
+    const int ia = a.oa[j], ib = a.ob[j];
+    const float inv_s = a.scales ? 1.f / a.scales[ia] : 1.f;
+    store_score(a.Uout, a.dtype, (long long)ia * a.V + g, u, inv_s);
+    if (ib >= 0) store_score(a.Uout, a.dtype, (long long)ib * a.V + g, cconj(u), inv_s);
+  } else if constexpr (SM == SM_ACCUM) {
+    const float p = a.psi[(long long)a.rows[j] * a.V + g];
+    acc = make_float2(acc.x + p * v.x, acc.y + p * v.y);
+  } else {  // SM_REAL
+    a.dst_r[g] = v.x * a.out_scale;
+  }
+}
+
+__device__ __forceinline__ void accum_flush(const PassArgs& a, long long g, float2 acc) {
+  float2 x = acc;
+  if (a.accumulate) x = cadd(a.dst_c[g], x);
+  a.dst_c[g] = x;
+}
+
 template <int R>
 __device__ __forceinline__ void stage(const PassArgs& a, const float2* __restrict__ cur, float2* __restrict__ nxt,
                                       int Ns, int nl) {
@@ -177,27 +230,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a) {
         }
         if (w < nl) {
           const long long g = gaddr(a, line0 + w, n);
-          float2 v;
-          if constexpr (LM == LM_REAL) {
-            v = make_float2(a.src_r[g], 0.f);
-          } else if constexpr (LM == LM_C) {
-            v = a.src_c[j * a.src_stride + g];
-          } else if constexpr (LM == LM_MULBANK) {
-            const float p = a.psi[(long long)a.rows[j] * a.V + g];
-            v = cscale(a.src_c[g], p);
-            asum += sqrtf(v.x * v.x + v.y * v.y);
-          } else if constexpr (LM == LM_UIN) {
-            const int ia = a.oa[j], ib = a.ob[j];
-            const float sa = a.scales ? a.scales[ia] : 1.f;
-            v = load_score(a.U, a.dtype, (long long)ia * a.V + g, sa);
-            if (ib >= 0) {
-              const float sb = a.scales ? a.scales[ib] : 1.f;
-              v = cadd(v, cconj(load_score(a.U, a.dtype, (long long)ib * a.V + g, sb)));
-            }
-          } else {  // LM_DIVM
-            v = a.src_c[g];
-            if (a.divide) v = cscale(v, 1.f / fmaxf(a.M[g], a.eps));
-          }
+          const float2 v = load_elem<LM>(a, j, g, asum);
           buf0[lidx(a.LS, w, n)] = v;
         }
       }
@@ -251,21 +284,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a) {
         }
         if (w < nl) {
           const long long g = gaddr(a, line0 + w, n);
-          const float2 v = cur[lidx(a.LS, w, n)];
-          if constexpr (SM == SM_C) {
-            a.dst_c[j * a.dst_stride + g] = v;
-          } else if constexpr (SM == SM_UOUT) {
-            const float2 u = cscale(v, a.out_scale);
-            const int ia = a.oa[j], ib = a.ob[j];
-            const float inv_s = a.scales ? 1.f / a.scales[ia] : 1.f;
-            store_score(a.Uout, a.dtype, (long long)ia * a.V + g, u, inv_s);
-            if (ib >= 0) store_score(a.Uout, a.dtype, (long long)ib * a.V + g, cconj(u), inv_s);
-          } else if constexpr (SM == SM_ACCUM) {
-            const float p = a.psi[(long long)a.rows[j] * a.V + g];
-            acc[e] = make_float2(acc[e].x + p * v.x, acc[e].y + p * v.y);
-          } else {  // SM_REAL
-            a.dst_r[g] = v.x * a.out_scale;
-          }
+          store_elem<SM>(a, j, g, cur[lidx(a.LS, w, n)], acc[e]);
         }
       }
     }
@@ -287,11 +306,117 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a) {
         }
         if (w < nl) {
           const long long g = gaddr(a, line0 + w, n);
-          float2 x = acc[e];
-          if (a.accumulate) x = cadd(a.dst_c[g], x);
-          a.dst_c[g] = x;
+          accum_flush(a, g, acc[e]);
         }
       }
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Power-of-two lines, N = 16 * R2 with R2 in {4, 8, 16}: every thread keeps
+// 16 elements of one line in registers.  Stage 1 is a radix-16 DFT of the
+// elements s + (N/16) r loaded straight from global memory; one LDS exchange
+// transposes the line; stage 2 applies the twiddles W_N^(j r) (LDS table) and
+// radix-R2 DFTs whose outputs are already in natural order, stored straight
+// to global memory.  Tiles are N/16 threads per line x (256 / (N/16)) lines.
+// ---------------------------------------------------------------------------
+template <int N>
+struct FastCfg {
+  static constexpr int TL = N / 16;        // threads per line
+  static constexpr int W = 256 / TL;       // lines per workgroup
+  static constexpr int R2 = N / 16;        // second-stage radix
+  static constexpr int B2 = 16 / R2;       // second-stage butterflies per thread
+  static constexpr int LS = N + N / 16 + 1;
+};
+
+__device__ __forceinline__ int padn(int n) { return n + (n >> 4); }
+
+template <int N, int AXIS>
+__device__ __forceinline__ long long gaddr_t(const PassArgs& a, long long line, int n) {
+  if constexpr (AXIS == 2) {
+    return line * N + n;
+  } else if constexpr (AXIS == 1) {
+    const long long z = line / a.Nx, x = line - z * a.Nx;
+    return (z * N + n) * a.Nx + x;
+  } else {
+    return (long long)n * a.Ny * a.Nx + line;
+  }
+}
+
+template <int N, int AXIS, int LM, int SM>
+__global__ __launch_bounds__(kThreads) void k_fast(PassArgs a) {
+  using C = FastCfg<N>;
+  __shared__ float2 buf[C::W * C::LS];
+  __shared__ float2 twl[N];
+  __shared__ float red[kThreads];
+  const int t = threadIdx.x;
+  int w, s;
+  if constexpr (AXIS == 2) {
+    s = t % C::TL;
+    w = t / C::TL;
+  } else {
+    w = t % C::W;
+    s = t / C::W;
+  }
+  const long long line = (long long)blockIdx.x * C::W + w;
+  const bool valid = line < a.lines;
+  for (int i = t; i < N; i += kThreads) {
+    float2 v = a.tw[i];
+    if (a.sgn > 0.f) v.y = -v.y;
+    twl[i] = v;
+  }
+  const int jb = (SM == SM_ACCUM) ? 0 : blockIdx.y;
+  const int je = (SM == SM_ACCUM) ? a.nb : blockIdx.y + 1;
+  float2 acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = make_float2(0.f, 0.f);
+  __syncthreads();
+
+  for (int j = jb; j < je; ++j) {
+    float2 v[16];
+    float asum = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      v[r] = valid ? load_elem<LM>(a, j, gaddr_t<N, AXIS>(a, line, s + C::TL * r), asum) : make_float2(0.f, 0.f);
+    if constexpr (LM == LM_MULBANK) {
+      if (a.partial) {
+        red[t] = asum;
+        __syncthreads();
+        for (int h = kThreads / 2; h > 0; h >>= 1) {
+          if (t < h) red[t] += red[t + h];
+          __syncthreads();
+        }
+        if (t == 0) a.partial[(long long)j * gridDim.x + blockIdx.x] = red[0];
+      }
+    }
+    dft16(v, a.sgn);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) buf[w * C::LS + padn(s * 16 + r)] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < C::B2; ++q) {
+      const int jj = s + C::TL * q;
+      float2 u[C::R2];
+#pragma unroll
+      for (int r = 0; r < C::R2; ++r) u[r] = buf[w * C::LS + padn(jj + 16 * r)];
+#pragma unroll
+      for (int r = 1; r < C::R2; ++r) u[r] = cmul(u[r], twl[jj * r]);
+      dft_r<C::R2>(u, a.sgn);
+      if (valid) {
+#pragma unroll
+        for (int r = 0; r < C::R2; ++r) store_elem<SM>(a, j, gaddr_t<N, AXIS>(a, line, jj + 16 * r), u[r], acc[q * C::R2 + r]);
+      }
+    }
+    __syncthreads();
+  }
+  if constexpr (SM == SM_ACCUM) {
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < C::B2; ++q)
+#pragma unroll
+        for (int r = 0; r < C::R2; ++r) accum_flush(a, gaddr_t<N, AXIS>(a, line, s + C::TL * q + 16 * r), acc[q * C::R2 + r]);
     }
   }
 }
@@ -351,17 +476,99 @@ static void setup_axis(const os3d_bank* b, int axis, PassArgs& a) {
 
 static size_t pass_lds(const PassArgs& a) { return (size_t)2 * a.W * a.LS * sizeof(float2); }
 
-template <int LM, int SM>
-static int run_pass(const PassArgs& a, int grid_y, hipStream_t st) {
-  const long long tiles = (a.lines + a.W - 1) / a.W;
-  const size_t lds = pass_lds(a);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_pass<LM, SM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-    attr_set = true;
+// Lines per workgroup of the kernel that run_pass launches for this pass.
+static int tile_lines(const PassArgs& a) {
+  if (a.N == 256) return FastCfg<256>::W;
+  if (a.N == 128) return FastCfg<128>::W;
+  if (a.N == 64) return FastCfg<64>::W;
+  return a.W;
+}
+
+// ---------------------------------------------------------------------------
+// Optional per-kernel timing: HIP events recorded on the launch stream around
+// every launch, with the algorithmic bytes each launch must move.
+// ---------------------------------------------------------------------------
+enum KernelId {
+  K_DFT_X, K_DFT_Y, K_DFT_Z, K_FWD_Z, K_SCALES, K_FWD_Y, K_FWD_X, K_REC_X, K_REC_Y, K_REC_Z,
+  K_FIN_Z, K_FIN_Y, K_FIN_X, K_BANK, K_COUNT
+};
+static_assert(K_BANK == PROF_BANK, "profiler slot of the bank kernel");
+static const char* kKernelNames[K_COUNT] = {
+    "dft_x_real_in", "dft_y", "dft_z", "fwd_z_mul_bank", "fwd_scales", "fwd_y", "fwd_x_store_scores",
+    "rec_x_load_scores", "rec_y", "rec_z_accumulate", "fin_z_divide_M", "fin_y", "fin_x_real_out",
+    "bank_synth_mfma"};
+
+struct ProfRec {
+  int kid;
+  hipEvent_t e0, e1;
+  double alg_bytes, alg_flops;
+};
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+
+void* prof_start(void* stream) {
+  if (!g_prof_on) return nullptr;
+  ProfRec* r = new ProfRec();
+  if (hipEventCreate(&r->e0) != hipSuccess || hipEventCreate(&r->e1) != hipSuccess) {
+    delete r;
+    return nullptr;
   }
-  hipLaunchKernelGGL((k_pass<LM, SM>), dim3((unsigned)tiles, grid_y), dim3(kThreads), lds, st, a);
-  return check_launch("k_pass");
+  (void)hipEventRecord(r->e0, (hipStream_t)stream);
+  return r;
+}
+
+void prof_stop(void* token, void* stream, int kid, double alg_bytes, double alg_flops) {
+  if (!token) return;
+  ProfRec* r = (ProfRec*)token;
+  (void)hipEventRecord(r->e1, (hipStream_t)stream);
+  r->kid = kid;
+  r->alg_bytes = alg_bytes;
+  r->alg_flops = alg_flops;
+  g_prof.push_back(*r);
+  delete r;
+}
+
+template <int LM, int SM, int N, int AXIS>
+static void launch_fast(const PassArgs& a, int grid_y, hipStream_t st) {
+  const long long tiles = (a.lines + FastCfg<N>::W - 1) / FastCfg<N>::W;
+  hipLaunchKernelGGL((k_fast<N, AXIS, LM, SM>), dim3((unsigned)tiles, grid_y), dim3(kThreads), 0, st, a);
+}
+
+template <int LM, int SM, int N>
+static void launch_fast_axis(const PassArgs& a, int grid_y, hipStream_t st) {
+  if (a.axis == 0) launch_fast<LM, SM, N, 0>(a, grid_y, st);
+  else if (a.axis == 1) launch_fast<LM, SM, N, 1>(a, grid_y, st);
+  else launch_fast<LM, SM, N, 2>(a, grid_y, st);
+}
+
+template <int LM, int SM>
+static int run_pass(int kid, double alg, const PassArgs& a, int grid_y, hipStream_t st) {
+  void* tok = prof_start(st);
+  if (a.N == 256) {
+    launch_fast_axis<LM, SM, 256>(a, grid_y, st);
+  } else if (a.N == 128) {
+    launch_fast_axis<LM, SM, 128>(a, grid_y, st);
+  } else if (a.N == 64) {
+    launch_fast_axis<LM, SM, 64>(a, grid_y, st);
+  } else {
+    const long long tiles = (a.lines + a.W - 1) / a.W;
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute((const void*)k_pass<LM, SM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+      attr_set = true;
+    }
+    hipLaunchKernelGGL((k_pass<LM, SM>), dim3((unsigned)tiles, grid_y), dim3(kThreads), pass_lds(a), st, a);
+  }
+  prof_stop(tok, st, kid, alg, 0.0);
+  return check_launch(kKernelNames[kid]);
+}
+
+// Algorithmic score bytes of one launch over nb stored rows: every stored
+// row stands for one orientation, or two with its antipode.
+static double score_bytes(const os3d_bank* b, const PassArgs& a, int nb, size_t ubytes) {
+  int n = 0;
+  for (int j = 0; j < nb; ++j) n += (a.ob[j] >= 0) ? 2 : 1;
+  return (double)n * (double)b->V * (double)ubytes;
 }
 
 static int pair_batch(const os3d_bank* b) {
@@ -376,7 +583,7 @@ size_t workspace_bytes(const os3d_bank* b) {
   for (int ax = 0; ax < 3; ++ax) {
     const int n = b->plan[ax].n;
     const int W = std::min(256, std::max(1, kTile / n));
-    max_tiles = std::max(max_tiles, (long long)((b->V / n + W - 1) / W));
+    max_tiles = std::max(max_tiles, (long long)((b->V / n + W - 1) / W));  // fast kernels use W = 4096 / n too
   }
   return (size_t)(1 + nb) * b->V * sizeof(float2) + (size_t)nb * max_tiles * sizeof(float) + 256;
 }
@@ -390,7 +597,7 @@ static int dft_real_volume(const os3d_bank* b, const float* f, float2* F, hipStr
   a.nb = 1;
   a.src_r = f;
   a.dst_c = F;
-  if ((rc = run_pass<LM_REAL, SM_C>(a, 1, st))) return rc;
+  if ((rc = run_pass<LM_REAL, SM_C>(K_DFT_X, 4.0 * b->V, a, 1, st))) return rc;
   for (int ax : {1, 0}) {
     PassArgs c = {};
     setup_axis(b, ax, c);
@@ -398,7 +605,7 @@ static int dft_real_volume(const os3d_bank* b, const float* f, float2* F, hipStr
     c.nb = 1;
     c.src_c = F;
     c.dst_c = F;
-    if ((rc = run_pass<LM_C, SM_C>(c, 1, st))) return rc;
+    if ((rc = run_pass<LM_C, SM_C>(ax == 1 ? K_DFT_Y : K_DFT_Z, 0.0, c, 1, st))) return rc;
   }
   return OS3D_OK;
 }
@@ -435,10 +642,12 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
       z.dst_stride = V;
       const bool quant = dtype != OS3D_C64;
       z.partial = quant ? partial : nullptr;
-      if ((rc = run_pass<LM_MULBANK, SM_C>(z, nb, st))) return rc;
+      if ((rc = run_pass<LM_MULBANK, SM_C>(K_FWD_Z, 0.0, z, nb, st))) return rc;
       if (quant) {
-        const long long tiles = (z.lines + z.W - 1) / z.W;
+        const long long tiles = (z.lines + tile_lines(z) - 1) / tile_lines(z);
+        void* tok = prof_start(st);
         hipLaunchKernelGGL(k_scales, dim3(nb), dim3(256), 0, st, partial, (int)tiles, z, dtype, sc);
+        prof_stop(tok, st, K_SCALES, 0.0, 0.0);
         if ((rc = check_launch("k_scales"))) return rc;
       }
       PassArgs y = {};
@@ -449,7 +658,7 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
       y.src_stride = V;
       y.dst_c = T;
       y.dst_stride = V;
-      if ((rc = run_pass<LM_C, SM_C>(y, nb, st))) return rc;
+      if ((rc = run_pass<LM_C, SM_C>(K_FWD_Y, 0.0, y, nb, st))) return rc;
       PassArgs x = {};
       setup_axis(b, 2, x);
       x.sgn = 1.f;
@@ -464,7 +673,7 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
       x.dtype = dtype;
       x.scales = quant ? sc : nullptr;
       x.out_scale = 1.f / (float)V;
-      if ((rc = run_pass<LM_C, SM_UOUT>(x, nb, st))) return rc;
+      if ((rc = run_pass<LM_C, SM_UOUT>(K_FWD_X, score_bytes(b, z, nb, ubytes), x, nb, st))) return rc;
     }
   }
   return OS3D_OK;
@@ -499,7 +708,7 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
       x.scales = (dtype == OS3D_C64) ? nullptr : sc;
       x.dst_c = T;
       x.dst_stride = V;
-      if ((rc = run_pass<LM_UIN, SM_C>(x, nb, st))) return rc;
+      if ((rc = run_pass<LM_UIN, SM_C>(K_REC_X, score_bytes(b, x, nb, ubytes), x, nb, st))) return rc;
       PassArgs y = {};
       setup_axis(b, 1, y);
       y.sgn = -1.f;
@@ -508,7 +717,7 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
       y.src_stride = V;
       y.dst_c = T;
       y.dst_stride = V;
-      if ((rc = run_pass<LM_C, SM_C>(y, nb, st))) return rc;
+      if ((rc = run_pass<LM_C, SM_C>(K_REC_Y, 0.0, y, nb, st))) return rc;
       PassArgs z = {};
       setup_axis(b, 0, z);
       z.sgn = -1.f;
@@ -519,7 +728,7 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
       z.psi = b->d.psi;
       z.dst_c = X;
       z.accumulate = (r0 > 0) ? 1 : 0;
-      if ((rc = run_pass<LM_C, SM_ACCUM>(z, 1, st))) return rc;
+      if ((rc = run_pass<LM_C, SM_ACCUM>(K_REC_Z, 0.0, z, 1, st))) return rc;
     }
     // X / max(M, eps) (reconstruction) or X (adjoint), inverse DFT, real part
     PassArgs z = {};
@@ -531,14 +740,14 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
     z.eps = (float)b->params.eps;
     z.divide = divide_M ? 1 : 0;
     z.dst_c = X;
-    if ((rc = run_pass<LM_DIVM, SM_C>(z, 1, st))) return rc;
+    if ((rc = run_pass<LM_DIVM, SM_C>(K_FIN_Z, 0.0, z, 1, st))) return rc;
     PassArgs y = {};
     setup_axis(b, 1, y);
     y.sgn = 1.f;
     y.nb = 1;
     y.src_c = X;
     y.dst_c = X;
-    if ((rc = run_pass<LM_C, SM_C>(y, 1, st))) return rc;
+    if ((rc = run_pass<LM_C, SM_C>(K_FIN_Y, 0.0, y, 1, st))) return rc;
     PassArgs x = {};
     setup_axis(b, 2, x);
     x.sgn = 1.f;
@@ -546,9 +755,43 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
     x.src_c = X;
     x.dst_r = f_out + (long long)bi * V;
     x.out_scale = 1.f / (float)V;
-    if ((rc = run_pass<LM_C, SM_REAL>(x, 1, st))) return rc;
+    if ((rc = run_pass<LM_C, SM_REAL>(K_FIN_X, 4.0 * b->V, x, 1, st))) return rc;
   }
   return OS3D_OK;
 }
+
+int profile_enable(int on) {
+  for (auto& r : g_prof) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  g_prof.clear();
+  g_prof_on = on != 0;
+  return OS3D_OK;
+}
+
+int profile_get(int idx, const char** name, long long* launches, double* total_ms, double* alg_bytes,
+                double* alg_flops) {
+  if (idx < 0 || idx >= K_COUNT) return OS3D_EINVAL;
+  *name = kKernelNames[idx];
+  long long n = 0;
+  double ms = 0.0, by = 0.0, fl = 0.0;
+  for (auto& r : g_prof) {
+    if (r.kid != idx) continue;
+    float t = 0.f;
+    if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&t, r.e0, r.e1) != hipSuccess) return OS3D_EDEVICE;
+    ++n;
+    ms += t;
+    by += r.alg_bytes;
+    fl += r.alg_flops;
+  }
+  *launches = n;
+  *total_ms = ms;
+  *alg_bytes = by;
+  *alg_flops = fl;
+  return OS3D_OK;
+}
+
+int profile_count() { return K_COUNT; }
 
 }  // namespace os3d

@@ -326,4 +326,23 @@ os3d_status os3d_reconstruct(const os3d_bank* b, const void* U, int32_t dtype, c
   return (os3d_status)launch_reduce(b, U, dtype, scales, batch, f_out, ws, true, stream);
 }
 
+os3d_status os3d_profile_enable(int32_t on) { return (os3d_status)profile_enable(on); }
+
+os3d_status os3d_profile_count(int32_t* n) {
+  if (!n) return (os3d_status)fail(OS3D_EINVAL, "n is NULL");
+  *n = profile_count();
+  return OS3D_OK;
+}
+
+os3d_status os3d_profile_get(int32_t idx, const char** name, int64_t* launches, double* total_ms, double* alg_bytes,
+                             double* alg_flops) {
+  if (!name || !launches || !total_ms || !alg_bytes || !alg_flops)
+    return (os3d_status)fail(OS3D_EINVAL, "output pointer is NULL");
+  long long n = 0;
+  int rc = profile_get(idx, name, &n, total_ms, alg_bytes, alg_flops);
+  *launches = n;
+  if (rc) return (os3d_status)fail(rc, "os3d_profile_get: bad index or event failure");
+  return OS3D_OK;
+}
+
 }  // extern "C"

@@ -108,6 +108,15 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
 int launch_export_psi(const os3d_bank* b, int i, float* out, void* stream);
 int launch_export_M(const os3d_bank* b, float* out, void* stream);
 size_t workspace_bytes(const os3d_bank* b);
+int profile_enable(int on);
+// Launch bracketing for the per-kernel timer: prof_start returns a token (or
+// null when timing is off); prof_stop records the launch under kernel slot kid.
+void* prof_start(void* stream);
+void prof_stop(void* token, void* stream, int kid, double alg_bytes, double alg_flops);
+enum ProfSlot { PROF_BANK = 13 };
+int profile_get(int idx, const char** name, long long* launches, double* total_ms, double* alg_bytes,
+                double* alg_flops);
+int profile_count();
 size_t bank_bytes(const int64_t dims[3], int n_unique, int L);
 void set_error(const std::string& msg);
 }  // namespace os3d

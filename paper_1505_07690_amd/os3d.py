@@ -57,6 +57,11 @@ _SIGS = {
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "os3d_reconstruct": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "os3d_profile_enable": [ctypes.c_int32],
+    "os3d_profile_count": [ctypes.POINTER(ctypes.c_int32)],
+    "os3d_profile_get": [ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64),
+                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_double)],
 }
 
 
@@ -271,3 +276,27 @@ def unpack16(Uq, scales, dtype):
     v = q.view(t).to(torch.float32)
     s = scales.reshape(scales.shape + (1,) * (Uq.dim() - scales.dim())).to(torch.float32)
     return torch.complex(v[..., 0] * s, v[..., 1] * s)
+
+
+def profile_enable(on=True):
+    """Per-kernel HIP-event timing inside the library (clears old records)."""
+    _check(lib().os3d_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """{kernel name: (launches, total ms, algorithmic bytes, algorithmic flops)}
+    of the records since profile_enable (waits for the recorded events)."""
+    n = ctypes.c_int32()
+    _check(lib().os3d_profile_count(ctypes.byref(n)))
+    out = {}
+    for i in range(n.value):
+        name = ctypes.c_char_p()
+        cnt = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        fl = ctypes.c_double()
+        _check(lib().os3d_profile_get(i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms), ctypes.byref(by),
+                                      ctypes.byref(fl)))
+        if cnt.value:
+            out[name.value.decode()] = (cnt.value, ms.value, by.value, fl.value)
+    return out

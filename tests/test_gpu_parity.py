@@ -54,6 +54,15 @@ CASES = {
     # a set without antipodes (no pairing) and the plate-detector variant
     "unpaired_plate": lambda: ((16, 12, 20), _random_orients(7, 3), _oracle_params(6, 7, "plate"),
                                inputs.tubes((16, 12, 20), 3, 1.5, 0.1, 0, 7)),
+    # power-of-two axes of the register-resident kernels (64 on every axis)
+    "fast64": lambda: ((64, 64, 64), inputs.icosahedral_orientations(0), _oracle_params(8, 12),
+                       inputs.tubes((64, 64, 64), 3, 1.5, 0.1, 0, 9)),
+    # 128 / 64 / 256 on z / y / x: each fast line length on a different axis, ragged tile count on none
+    "fast128x64x256": lambda: ((128, 64, 256), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
+                               inputs.tubes((128, 64, 256), 3, 1.5, 0.1, 0, 10)),
+    # 256 on z, 128 on y, tiny x: a y-tile wraps across z planes
+    "fast256x128x4": lambda: ((256, 128, 4), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
+                              inputs.tubes((256, 128, 4), 2, 1.0, 0.1, 0, 11)),
     # small N with radix-2 only and a long axis
     "long4x6x64": lambda: ((4, 6, 64), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                            inputs.tubes((4, 6, 64), 2, 1.0, 0.1, 0, 8)),
