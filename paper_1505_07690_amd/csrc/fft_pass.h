@@ -1,0 +1,167 @@
+// Arguments and fused per-value loads and stores shared by the DFT pass
+// kernels (the three-pass path of kernels_fft.hip and the two-pass 256^3 path
+// of kernels_fft4.hip).
+#pragma once
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "fft_radix.h"
+#include "os3d_internal.h"
+
+namespace os3d {
+
+constexpr int kMaxBatch = 16;    // orientation pairs per launch
+
+enum LoadMode { LM_REAL = 0, LM_C = 1, LM_MULBANK = 2, LM_UIN = 3, LM_DIVM = 4 };
+enum StoreMode { SM_C = 0, SM_UOUT = 1, SM_ACCUM = 2, SM_REAL = 3 };
+
+struct PassArgs {
+  int axis;  // 0 = z, 1 = y, 2 = x
+  int Nz, Ny, Nx;
+  long long V;
+  int N, nst;
+  int radix[kMaxStages];
+  int W, LS;            // lines per tile, LDS line stride (float2)
+  long long lines;      // V / N
+  const float2* tw;     // exp(-2 pi i j / N)
+  float sgn;            // -1: forward DFT, +1: inverse DFT
+  int nb;               // pairs in this launch
+  // sources
+  const float* src_r;
+  const float2* src_c;
+  long long src_stride;  // per pair (elements)
+  const float* psi;      // bank rows
+  int rows[kMaxBatch];
+  int oa[kMaxBatch], ob[kMaxBatch];  // stored member, partner (-1 if none)
+  const void* U;
+  int dtype;
+  const float* scales;   // [N_o] of this volume
+  const float* M;
+  float eps;
+  int divide;
+  // destinations
+  float2* dst_c;
+  long long dst_stride;
+  float* dst_r;
+  void* Uout;
+  float out_scale;
+  float* partial;        // [nb][tiles] sums of |value| (scale bound), or null
+  int accumulate;        // SM_ACCUM: 1 adds to X, 0 overwrites
+};
+
+__device__ __forceinline__ long long gaddr(const PassArgs& a, long long line, int n) {
+  if (a.axis == 2) return line * a.Nx + n;
+  if (a.axis == 1) {
+    long long z = line / a.Nx, x = line - z * a.Nx;
+    return (z * a.Ny + n) * a.Nx + x;
+  }
+  return (long long)n * a.Ny * a.Nx + line;
+}
+
+__device__ __forceinline__ int lidx(int LS, int w, int n) { return w * LS + n + (n >> 4); }
+
+__device__ __forceinline__ float2 load_score(const void* U, int dtype, long long i, float s) {
+  if (dtype == OS3D_C64) return ((const float2*)U)[i];
+  const unsigned int q = ((const unsigned int*)U)[i];
+  float re, im;
+  if (dtype == OS3D_F16X2) {
+    re = __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
+    im = __half2float(__ushort_as_half((unsigned short)(q >> 16)));
+  } else {
+    re = __uint_as_float((q & 0xffffu) << 16);
+    im = __uint_as_float(q & 0xffff0000u);
+  }
+  return make_float2(re * s, im * s);
+}
+
+__device__ __forceinline__ unsigned int bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  unsigned int lsb = (u >> 16) & 1u;
+  return (u + 0x7fffu + lsb) >> 16;
+}
+
+__device__ __forceinline__ void store_score(void* U, int dtype, long long i, float2 v, float inv_s) {
+  if (dtype == OS3D_C64) {
+    ((float2*)U)[i] = v;
+    return;
+  }
+  float re = v.x * inv_s, im = v.y * inv_s;
+  unsigned int q;
+  if (dtype == OS3D_F16X2)
+    q = (unsigned int)__half_as_ushort(__float2half_rn(re)) | ((unsigned int)__half_as_ushort(__float2half_rn(im)) << 16);
+  else
+    q = bf16_rne(re) | (bf16_rne(im) << 16);
+  ((unsigned int*)U)[i] = q;
+}
+
+// Fused first-pass load of element g (line position) for pair slot j.
+template <int LM>
+__device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long g, float& asum) {
+  if constexpr (LM == LM_REAL) {
+    return make_float2(a.src_r[g], 0.f);
+  } else if constexpr (LM == LM_C) {
+    return a.src_c[j * a.src_stride + g];
+  } else if constexpr (LM == LM_MULBANK) {
+    const float p = a.psi[(long long)a.rows[j] * a.V + g];
+    const float2 v = cscale(a.src_c[g], p);
+    asum += sqrtf(v.x * v.x + v.y * v.y);
+    return v;
+  } else if constexpr (LM == LM_UIN) {
+    const int ia = a.oa[j], ib = a.ob[j];
+    const float sa = a.scales ? a.scales[ia] : 1.f;
+    float2 v = load_score(a.U, a.dtype, (long long)ia * a.V + g, sa);
+    if (ib >= 0) {
+      const float sb = a.scales ? a.scales[ib] : 1.f;
+      v = cadd(v, cconj(load_score(a.U, a.dtype, (long long)ib * a.V + g, sb)));
+    }
+    return v;
+  } else {  // LM_DIVM
+    float2 v = a.src_c[g];
+    if (a.divide) v = cscale(v, 1.f / fmaxf(a.M[g], a.eps));
+    return v;
+  }
+}
+
+// Fused last-pass store of element g for pair slot j (SM_ACCUM adds into acc).
+template <int SM>
+__device__ __forceinline__ void store_elem(const PassArgs& a, int j, long long g, float2 v, float2& acc) {
+  if constexpr (SM == SM_C) {
+    a.dst_c[j * a.dst_stride + g] = v;
+  } else if constexpr (SM == SM_UOUT) {
+    const float2 u = cscale(v, a.out_scale);
+    const int ia = a.oa[j], ib = a.ob[j];
+    const float inv_s = a.scales ? 1.f / a.scales[ia] : 1.f;
+    store_score(a.Uout, a.dtype, (long long)ia * a.V + g, u, inv_s);
+    if (ib >= 0) store_score(a.Uout, a.dtype, (long long)ib * a.V + g, cconj(u), inv_s);
+  } else if constexpr (SM == SM_ACCUM) {
+    const float p = a.psi[(long long)a.rows[j] * a.V + g];
+    acc = make_float2(acc.x + p * v.x, acc.y + p * v.y);
+  } else {  // SM_REAL
+    a.dst_r[g] = v.x * a.out_scale;
+  }
+}
+
+__device__ __forceinline__ void accum_flush(const PassArgs& a, long long g, float2 acc) {
+  float2 x = acc;
+  if (a.accumulate) x = cadd(a.dst_c[g], x);
+  a.dst_c[g] = x;
+}
+
+
+// Per-kernel timer slots (os3d_profile_*): first / middle / last pass of the
+// DFT of f, of the forward transform, of the reconstruction's orientation
+// sum and of its final inverse DFT.
+enum ProfKernel {
+  kProfDftFirst = 0, kProfDftMid, kProfDftLast, kProfFwdFirst, kProfScales, kProfFwdMid, kProfFwdLast,
+  kProfRecFirst, kProfRecMid, kProfRecLast, kProfInvFirst, kProfInvMid, kProfInvLast, kProfBank, kProfCount
+};
+
+void launch_scales(const float* partial, int ntiles, const PassArgs& a, int dtype, float* scales, int nb,
+                   hipStream_t st);
+int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, float* scales, void* ws, int nbmax,
+             void* stream);
+int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out, void* ws,
+            bool divide_M, int nbmax, void* stream);
+
+}  // namespace os3d

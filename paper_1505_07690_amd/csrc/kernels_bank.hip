@@ -16,6 +16,7 @@
 
 #include <algorithm>
 
+#include "layout4.h"
 #include "os3d_internal.h"
 
 namespace os3d {
@@ -27,6 +28,7 @@ constexpr int kYStride = 272;   // LDS row stride (floats) of the K-chunk buffer
 constexpr int kColsPerSweep = 128;
 
 struct BankArgs {
+  int layout;  // storage order of the frequency points (natural or four-step tiles)
   int Nz, Ny, Nx;
   long long V;
   int L, Npad, n_rows;
@@ -78,9 +80,8 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
   double ux = 0.0, uy = 0.0, uz = 1.0, g = 0.0;
   int dc = 0;
   if (valid) {
-    int kx = (int)(p % a.Nx);
-    int ky = (int)((p / a.Nx) % a.Ny);
-    int kz = (int)(p / ((long long)a.Nx * a.Ny));
+    int kz, ky, kx;
+    pos_to_k(a.layout, p, a.Nz, a.Ny, a.Nx, kz, ky, kx);
     double wx = omega_of(kx, a.Nx), wy = omega_of(ky, a.Ny), wz = omega_of(kz, a.Nz);
     double r2 = wx * wx + wy * wy + wz * wz;
     if (r2 > 0.0) {
@@ -200,21 +201,17 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
   }
 }
 
-// S: k -> -k mod N on every axis.
-__device__ inline long long mirror_index(long long p, int Nz, int Ny, int Nx) {
-  int kx = (int)(p % Nx);
-  int ky = (int)((p / Nx) % Ny);
-  int kz = (int)(p / ((long long)Nx * Ny));
-  kx = (Nx - kx) % Nx;
-  ky = (Ny - ky) % Ny;
-  kz = (Nz - kz) % Nz;
-  return ((long long)kz * Ny + ky) * Nx + kx;
+// S: k -> -k mod N on every axis, on storage positions.
+__device__ inline long long mirror_index(int layout, long long p, int Nz, int Ny, int Nx) {
+  int kz, ky, kx;
+  pos_to_k(layout, p, Nz, Ny, Nx, kz, ky, kx);
+  return k_to_pos(layout, (Nz - kz) % Nz, (Ny - ky) % Ny, (Nx - kx) % Nx, Ny, Nx);
 }
 
 // Partial sums over the band (rho <= rho_N / 2, no Nyquist plane, k != 0) of
 // the un-normalised M0[k] = Mh[k] (+ Mh[-k] for antipodal pairs).
-__global__ __launch_bounds__(256) void k_kappa_partial(const double* Mh, int paired, int Nz, int Ny, int Nx,
-                                                       long long V, double* part) {
+__global__ __launch_bounds__(256) void k_kappa_partial(const double* Mh, int paired, int layout, int Nz, int Ny,
+                                                       int Nx, long long V, double* part) {
   __shared__ double ssum[256];
   __shared__ double scnt[256];
   const int tid = threadIdx.x;
@@ -223,14 +220,13 @@ __global__ __launch_bounds__(256) void k_kappa_partial(const double* Mh, int pai
   double s = 0.0, cnt = 0.0;
   const double half = 0.5 * 3.14159265358979323846;
   for (long long p = b + tid; p < e; p += 256) {
-    int kx = (int)(p % Nx);
-    int ky = (int)((p / Nx) % Ny);
-    int kz = (int)(p / ((long long)Nx * Ny));
+    int kz, ky, kx;
+    pos_to_k(layout, p, Nz, Ny, Nx, kz, ky, kx);
     if (is_nyquist(kx, Nx) || is_nyquist(ky, Ny) || is_nyquist(kz, Nz)) continue;
     double wx = omega_of(kx, Nx), wy = omega_of(ky, Ny), wz = omega_of(kz, Nz);
     double rho = sqrt(wx * wx + wy * wy + wz * wz);
     if (rho > 0.0 && rho <= half) {
-      double m0 = Mh[p] + (paired ? Mh[mirror_index(p, Nz, Ny, Nx)] : 0.0);
+      double m0 = Mh[p] + (paired ? Mh[mirror_index(layout, p, Nz, Ny, Nx)] : 0.0);
       s += m0;
       cnt += 1.0;
     }
@@ -264,22 +260,34 @@ __global__ void k_kappa_final(double* part, int nparts) {
 
 // psi *= kappa; M = kappa^2 M0.
 __global__ __launch_bounds__(256) void k_bank_finalize(float* psi, int n_rows, double* Mh, float* M, int paired,
-                                                       int Nz, int Ny, int Nx, long long V, const double* kappa_p) {
+                                                       int layout, int Nz, int Ny, int Nx, long long V,
+                                                       const double* kappa_p) {
   const double kappa = *kappa_p;
   const float kf = (float)kappa;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < V; p += stride) {
-    double m0 = Mh[p] + (paired ? Mh[mirror_index(p, Nz, Ny, Nx)] : 0.0);
+    double m0 = Mh[p] + (paired ? Mh[mirror_index(layout, p, Nz, Ny, Nx)] : 0.0);
     M[p] = (float)(kappa * kappa * m0);
     for (int r = 0; r < n_rows; ++r) psi[(long long)r * V + p] *= kf;
   }
 }
 
-__global__ __launch_bounds__(256) void k_export_psi(const float* row, int mirrored, int Nz, int Ny, int Nx, long long V,
-                                                    float* out) {
+// Natural-order export: out[k] = row[pos(k)] (or row[pos(-k)] for the
+// second member of an antipodal pair).
+__global__ __launch_bounds__(256) void k_export(const float* row, int mirrored, int layout, int Nz, int Ny, int Nx,
+                                                long long V, float* out) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < V; p += stride)
-    out[p] = row[mirrored ? mirror_index(p, Nz, Ny, Nx) : p];
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < V; p += stride) {
+    int kx = (int)(p % Nx);
+    int ky = (int)((p / Nx) % Ny);
+    int kz = (int)(p / ((long long)Nx * Ny));
+    if (mirrored) {
+      kx = (Nx - kx) % Nx;
+      ky = (Ny - ky) % Ny;
+      kz = (Nz - kz) % Nz;
+    }
+    out[p] = row[k_to_pos(layout, kz, ky, kx, Ny, Nx)];
+  }
 }
 
 static int check_launch(const char* what) {
@@ -295,6 +303,7 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const int L = b->L, nn = L + 1;
   BankArgs a;
+  a.layout = b->layout;
   a.Nz = (int)b->dims[0];
   a.Ny = (int)b->dims[1];
   a.Nx = (int)b->dims[2];
@@ -330,14 +339,14 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   int rc = check_launch("k_bank_synth");
   if (rc) return rc;
   const int nparts = 1024;
-  hipLaunchKernelGGL(k_kappa_partial, dim3(nparts), dim3(256), 0, st, b->d.Mh, b->paired, a.Nz, a.Ny, a.Nx, a.V,
-                     b->d.part);
+  hipLaunchKernelGGL(k_kappa_partial, dim3(nparts), dim3(256), 0, st, b->d.Mh, b->paired, b->layout, a.Nz, a.Ny,
+                     a.Nx, a.V, b->d.part);
   if ((rc = check_launch("k_kappa_partial"))) return rc;
   hipLaunchKernelGGL(k_kappa_final, dim3(1), dim3(64), 0, st, b->d.part, nparts);
   if ((rc = check_launch("k_kappa_final"))) return rc;
   const unsigned fin_blocks = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
   hipLaunchKernelGGL(k_bank_finalize, dim3(fin_blocks), dim3(256), 0, st, b->d.psi, b->n_unique, b->d.Mh, b->d.M,
-                     b->paired, a.Nz, a.Ny, a.Nx, a.V, b->d.part + 2 * nparts);
+                     b->paired, b->layout, a.Nz, a.Ny, a.Nx, a.V, b->d.part + 2 * nparts);
   if ((rc = check_launch("k_bank_finalize"))) return rc;
   double kappa = 0.0;
   if (hipMemcpyAsync(&kappa, b->d.part + 2 * nparts, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -352,17 +361,16 @@ int launch_build_bank(os3d_bank* b, void* stream) {
 int launch_export_psi(const os3d_bank* b, int i, float* out, void* stream) {
   const float* row = b->d.psi + (long long)b->row_of[i] * b->V;
   const unsigned nb = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_export_psi, dim3(nb), dim3(256), 0, (hipStream_t)stream, row, b->conj_of[i], (int)b->dims[0],
-                     (int)b->dims[1], (int)b->dims[2], b->V, out);
-  return check_launch("k_export_psi");
+  hipLaunchKernelGGL(k_export, dim3(nb), dim3(256), 0, (hipStream_t)stream, row, b->conj_of[i], b->layout,
+                     (int)b->dims[0], (int)b->dims[1], (int)b->dims[2], b->V, out);
+  return check_launch("k_export");
 }
 
 int launch_export_M(const os3d_bank* b, float* out, void* stream) {
-  if (hipMemcpyAsync(out, b->d.M, b->V * sizeof(float), hipMemcpyDeviceToDevice, (hipStream_t)stream) != hipSuccess) {
-    set_error("os3d_bank_M: copy failed");
-    return OS3D_EDEVICE;
-  }
-  return OS3D_OK;
+  const unsigned nb = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_export, dim3(nb), dim3(256), 0, (hipStream_t)stream, b->d.M, 0, b->layout, (int)b->dims[0],
+                     (int)b->dims[1], (int)b->dims[2], b->V, out);
+  return check_launch("k_export");
 }
 
 }  // namespace os3d

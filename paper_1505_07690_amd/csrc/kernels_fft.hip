@@ -13,157 +13,19 @@
 //   * pair load U_n + conj(U_{-n}) and the weighted orientation sum
 //     X += psi_hat_n * DFT(.) over a batch of pairs (Eq. 8),
 //   * X / max(M, eps) (Sec. 3.1) and the real part of the inverse.
-#include <hip/hip_bf16.h>
-#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdlib>
 
-#include "fft_radix.h"
-#include "os3d_internal.h"
+#include "fft_pass.h"
+#include "layout4.h"
 
 namespace os3d {
 
 constexpr int kThreads = 256;
 constexpr int kTile = 4096;      // complex elements per workgroup tile
 constexpr int kEPT = kTile / kThreads;
-constexpr int kMaxBatch = 16;    // orientation pairs per launch
-
-enum LoadMode { LM_REAL = 0, LM_C = 1, LM_MULBANK = 2, LM_UIN = 3, LM_DIVM = 4 };
-enum StoreMode { SM_C = 0, SM_UOUT = 1, SM_ACCUM = 2, SM_REAL = 3 };
-
-struct PassArgs {
-  int axis;  // 0 = z, 1 = y, 2 = x
-  int Nz, Ny, Nx;
-  long long V;
-  int N, nst;
-  int radix[kMaxStages];
-  int W, LS;            // lines per tile, LDS line stride (float2)
-  long long lines;      // V / N
-  const float2* tw;     // exp(-2 pi i j / N)
-  float sgn;            // -1: forward DFT, +1: inverse DFT
-  int nb;               // pairs in this launch
-  // sources
-  const float* src_r;
-  const float2* src_c;
-  long long src_stride;  // per pair (elements)
-  const float* psi;      // bank rows
-  int rows[kMaxBatch];
-  int oa[kMaxBatch], ob[kMaxBatch];  // stored member, partner (-1 if none)
-  const void* U;
-  int dtype;
-  const float* scales;   // [N_o] of this volume
-  const float* M;
-  float eps;
-  int divide;
-  // destinations
-  float2* dst_c;
-  long long dst_stride;
-  float* dst_r;
-  void* Uout;
-  float out_scale;
-  float* partial;        // [nb][tiles] sums of |value| (scale bound), or null
-  int accumulate;        // SM_ACCUM: 1 adds to X, 0 overwrites
-};
-
-__device__ __forceinline__ long long gaddr(const PassArgs& a, long long line, int n) {
-  if (a.axis == 2) return line * a.Nx + n;
-  if (a.axis == 1) {
-    long long z = line / a.Nx, x = line - z * a.Nx;
-    return (z * a.Ny + n) * a.Nx + x;
-  }
-  return (long long)n * a.Ny * a.Nx + line;
-}
-
-__device__ __forceinline__ int lidx(int LS, int w, int n) { return w * LS + n + (n >> 4); }
-
-__device__ __forceinline__ float2 load_score(const void* U, int dtype, long long i, float s) {
-  if (dtype == OS3D_C64) return ((const float2*)U)[i];
-  const unsigned int q = ((const unsigned int*)U)[i];
-  float re, im;
-  if (dtype == OS3D_F16X2) {
-    re = __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
-    im = __half2float(__ushort_as_half((unsigned short)(q >> 16)));
-  } else {
-    re = __uint_as_float((q & 0xffffu) << 16);
-    im = __uint_as_float(q & 0xffff0000u);
-  }
-  return make_float2(re * s, im * s);
-}
-
-__device__ __forceinline__ unsigned int bf16_rne(float x) {
-  unsigned int u = __float_as_uint(x);
-  unsigned int lsb = (u >> 16) & 1u;
-  return (u + 0x7fffu + lsb) >> 16;
-}
-
-__device__ __forceinline__ void store_score(void* U, int dtype, long long i, float2 v, float inv_s) {
-  if (dtype == OS3D_C64) {
-    ((float2*)U)[i] = v;
-    return;
-  }
-  float re = v.x * inv_s, im = v.y * inv_s;
-  unsigned int q;
-  if (dtype == OS3D_F16X2)
-    q = (unsigned int)__half_as_ushort(__float2half_rn(re)) | ((unsigned int)__half_as_ushort(__float2half_rn(im)) << 16);
-  else
-    q = bf16_rne(re) | (bf16_rne(im) << 16);
-  ((unsigned int*)U)[i] = q;
-}
-
-// Fused first-pass load of element g (line position) for pair slot j.
-template <int LM>
-__device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long g, float& asum) {
-  if constexpr (LM == LM_REAL) {
-    return make_float2(a.src_r[g], 0.f);
-  } else if constexpr (LM == LM_C) {
-    return a.src_c[j * a.src_stride + g];
-  } else if constexpr (LM == LM_MULBANK) {
-    const float p = a.psi[(long long)a.rows[j] * a.V + g];
-    const float2 v = cscale(a.src_c[g], p);
-    asum += sqrtf(v.x * v.x + v.y * v.y);
-    return v;
-  } else if constexpr (LM == LM_UIN) {
-    const int ia = a.oa[j], ib = a.ob[j];
-    const float sa = a.scales ? a.scales[ia] : 1.f;
-    float2 v = load_score(a.U, a.dtype, (long long)ia * a.V + g, sa);
-    if (ib >= 0) {
-      const float sb = a.scales ? a.scales[ib] : 1.f;
-      v = cadd(v, cconj(load_score(a.U, a.dtype, (long long)ib * a.V + g, sb)));
-    }
-    return v;
-  } else {  // LM_DIVM
-    float2 v = a.src_c[g];
-    if (a.divide) v = cscale(v, 1.f / fmaxf(a.M[g], a.eps));
-    return v;
-  }
-}
-
-// Fused last-pass store of element g for pair slot j (SM_ACCUM adds into acc).
-template <int SM>
-__device__ __forceinline__ void store_elem(const PassArgs& a, int j, long long g, float2 v, float2& acc) {
-  if constexpr (SM == SM_C) {
-    a.dst_c[j * a.dst_stride + g] = v;
-  } else if constexpr (SM == SM_UOUT) {
-    const float2 u = cscale(v, a.out_scale);
-    const int ia = a.oa[j], ib = a.ob[j];
-    const float inv_s = a.scales ? 1.f / a.scales[ia] : 1.f;
-    store_score(a.Uout, a.dtype, (long long)ia * a.V + g, u, inv_s);
-    if (ib >= 0) store_score(a.Uout, a.dtype, (long long)ib * a.V + g, cconj(u), inv_s);
-  } else if constexpr (SM == SM_ACCUM) {
-    const float p = a.psi[(long long)a.rows[j] * a.V + g];
-    acc = make_float2(acc.x + p * v.x, acc.y + p * v.y);
-  } else {  // SM_REAL
-    a.dst_r[g] = v.x * a.out_scale;
-  }
-}
-
-__device__ __forceinline__ void accum_flush(const PassArgs& a, long long g, float2 acc) {
-  float2 x = acc;
-  if (a.accumulate) x = cadd(a.dst_c[g], x);
-  a.dst_c[g] = x;
-}
 
 template <int R>
 __device__ __forceinline__ void stage(const PassArgs& a, const float2* __restrict__ cur, float2* __restrict__ nxt,
@@ -449,6 +311,11 @@ __global__ __launch_bounds__(256) void k_scales(const float* partial, int ntiles
   }
 }
 
+void launch_scales(const float* partial, int ntiles, const PassArgs& a, int dtype, float* scales, int nb,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_scales, dim3(nb), dim3(256), 0, st, partial, ntiles, a, dtype, scales);
+}
+
 static int check_launch(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -488,15 +355,11 @@ static int tile_lines(const PassArgs& a) {
 // Optional per-kernel timing: HIP events recorded on the launch stream around
 // every launch, with the algorithmic bytes each launch must move.
 // ---------------------------------------------------------------------------
-enum KernelId {
-  K_DFT_X, K_DFT_Y, K_DFT_Z, K_FWD_Z, K_SCALES, K_FWD_Y, K_FWD_X, K_REC_X, K_REC_Y, K_REC_Z,
-  K_FIN_Z, K_FIN_Y, K_FIN_X, K_BANK, K_COUNT
-};
-static_assert(K_BANK == PROF_BANK, "profiler slot of the bank kernel");
-static const char* kKernelNames[K_COUNT] = {
-    "dft_x_real_in", "dft_y", "dft_z", "fwd_z_mul_bank", "fwd_scales", "fwd_y", "fwd_x_store_scores",
-    "rec_x_load_scores", "rec_y", "rec_z_accumulate", "fin_z_divide_M", "fin_y", "fin_x_real_out",
-    "bank_synth_mfma"};
+static_assert((int)kProfBank == (int)PROF_BANK, "profiler slot of the bank kernel");
+static const char* kKernelNames[kProfCount] = {
+    "dft_f_first_real_in", "dft_f_mid", "dft_f_last", "fwd_first_mul_bank", "fwd_scales", "fwd_mid",
+    "fwd_last_store_scores", "rec_first_load_scores", "rec_mid", "rec_last_accumulate", "inv_first_divide_M",
+    "inv_mid", "inv_last_real_out", "bank_synth_mfma"};
 
 struct ProfRec {
   int kid;
@@ -597,7 +460,7 @@ static int dft_real_volume(const os3d_bank* b, const float* f, float2* F, hipStr
   a.nb = 1;
   a.src_r = f;
   a.dst_c = F;
-  if ((rc = run_pass<LM_REAL, SM_C>(K_DFT_X, 4.0 * b->V, a, 1, st))) return rc;
+  if ((rc = run_pass<LM_REAL, SM_C>(kProfDftFirst, 4.0 * b->V, a, 1, st))) return rc;
   for (int ax : {1, 0}) {
     PassArgs c = {};
     setup_axis(b, ax, c);
@@ -605,13 +468,14 @@ static int dft_real_volume(const os3d_bank* b, const float* f, float2* F, hipStr
     c.nb = 1;
     c.src_c = F;
     c.dst_c = F;
-    if ((rc = run_pass<LM_C, SM_C>(ax == 1 ? K_DFT_Y : K_DFT_Z, 0.0, c, 1, st))) return rc;
+    if ((rc = run_pass<LM_C, SM_C>(ax == 1 ? kProfDftMid : kProfDftLast, 0.0, c, 1, st))) return rc;
   }
   return OS3D_OK;
 }
 
 int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int dtype, float* scales, void* ws,
                    void* stream) {
+  if (b->layout == kLayoutFour256) return forward4(b, f, batch, U, dtype, scales, ws, pair_batch(b), stream);
   hipStream_t st = (hipStream_t)stream;
   const long long V = b->V;
   const int nbmax = pair_batch(b);
@@ -642,12 +506,12 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
       z.dst_stride = V;
       const bool quant = dtype != OS3D_C64;
       z.partial = quant ? partial : nullptr;
-      if ((rc = run_pass<LM_MULBANK, SM_C>(K_FWD_Z, 0.0, z, nb, st))) return rc;
+      if ((rc = run_pass<LM_MULBANK, SM_C>(kProfFwdFirst, 0.0, z, nb, st))) return rc;
       if (quant) {
         const long long tiles = (z.lines + tile_lines(z) - 1) / tile_lines(z);
         void* tok = prof_start(st);
         hipLaunchKernelGGL(k_scales, dim3(nb), dim3(256), 0, st, partial, (int)tiles, z, dtype, sc);
-        prof_stop(tok, st, K_SCALES, 0.0, 0.0);
+        prof_stop(tok, st, kProfScales, 0.0, 0.0);
         if ((rc = check_launch("k_scales"))) return rc;
       }
       PassArgs y = {};
@@ -658,7 +522,7 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
       y.src_stride = V;
       y.dst_c = T;
       y.dst_stride = V;
-      if ((rc = run_pass<LM_C, SM_C>(K_FWD_Y, 0.0, y, nb, st))) return rc;
+      if ((rc = run_pass<LM_C, SM_C>(kProfFwdMid, 0.0, y, nb, st))) return rc;
       PassArgs x = {};
       setup_axis(b, 2, x);
       x.sgn = 1.f;
@@ -673,7 +537,7 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
       x.dtype = dtype;
       x.scales = quant ? sc : nullptr;
       x.out_scale = 1.f / (float)V;
-      if ((rc = run_pass<LM_C, SM_UOUT>(K_FWD_X, score_bytes(b, z, nb, ubytes), x, nb, st))) return rc;
+      if ((rc = run_pass<LM_C, SM_UOUT>(kProfFwdLast, score_bytes(b, z, nb, ubytes), x, nb, st))) return rc;
     }
   }
   return OS3D_OK;
@@ -681,6 +545,8 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
 
 int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out,
                   void* ws, bool divide_M, void* stream) {
+  if (b->layout == kLayoutFour256)
+    return reduce4(b, U, dtype, scales, batch, f_out, ws, divide_M, pair_batch(b), stream);
   hipStream_t st = (hipStream_t)stream;
   const long long V = b->V;
   const int nbmax = pair_batch(b);
@@ -708,7 +574,7 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
       x.scales = (dtype == OS3D_C64) ? nullptr : sc;
       x.dst_c = T;
       x.dst_stride = V;
-      if ((rc = run_pass<LM_UIN, SM_C>(K_REC_X, score_bytes(b, x, nb, ubytes), x, nb, st))) return rc;
+      if ((rc = run_pass<LM_UIN, SM_C>(kProfRecFirst, score_bytes(b, x, nb, ubytes), x, nb, st))) return rc;
       PassArgs y = {};
       setup_axis(b, 1, y);
       y.sgn = -1.f;
@@ -717,7 +583,7 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
       y.src_stride = V;
       y.dst_c = T;
       y.dst_stride = V;
-      if ((rc = run_pass<LM_C, SM_C>(K_REC_Y, 0.0, y, nb, st))) return rc;
+      if ((rc = run_pass<LM_C, SM_C>(kProfRecMid, 0.0, y, nb, st))) return rc;
       PassArgs z = {};
       setup_axis(b, 0, z);
       z.sgn = -1.f;
@@ -728,7 +594,7 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
       z.psi = b->d.psi;
       z.dst_c = X;
       z.accumulate = (r0 > 0) ? 1 : 0;
-      if ((rc = run_pass<LM_C, SM_ACCUM>(K_REC_Z, 0.0, z, 1, st))) return rc;
+      if ((rc = run_pass<LM_C, SM_ACCUM>(kProfRecLast, 0.0, z, 1, st))) return rc;
     }
     // X / max(M, eps) (reconstruction) or X (adjoint), inverse DFT, real part
     PassArgs z = {};
@@ -740,14 +606,14 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
     z.eps = (float)b->params.eps;
     z.divide = divide_M ? 1 : 0;
     z.dst_c = X;
-    if ((rc = run_pass<LM_DIVM, SM_C>(K_FIN_Z, 0.0, z, 1, st))) return rc;
+    if ((rc = run_pass<LM_DIVM, SM_C>(kProfInvFirst, 0.0, z, 1, st))) return rc;
     PassArgs y = {};
     setup_axis(b, 1, y);
     y.sgn = 1.f;
     y.nb = 1;
     y.src_c = X;
     y.dst_c = X;
-    if ((rc = run_pass<LM_C, SM_C>(K_FIN_Y, 0.0, y, 1, st))) return rc;
+    if ((rc = run_pass<LM_C, SM_C>(kProfInvMid, 0.0, y, 1, st))) return rc;
     PassArgs x = {};
     setup_axis(b, 2, x);
     x.sgn = 1.f;
@@ -755,7 +621,7 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
     x.src_c = X;
     x.dst_r = f_out + (long long)bi * V;
     x.out_scale = 1.f / (float)V;
-    if ((rc = run_pass<LM_C, SM_REAL>(K_FIN_X, 4.0 * b->V, x, 1, st))) return rc;
+    if ((rc = run_pass<LM_C, SM_REAL>(kProfInvLast, 4.0 * b->V, x, 1, st))) return rc;
   }
   return OS3D_OK;
 }
@@ -772,7 +638,7 @@ int profile_enable(int on) {
 
 int profile_get(int idx, const char** name, long long* launches, double* total_ms, double* alg_bytes,
                 double* alg_flops) {
-  if (idx < 0 || idx >= K_COUNT) return OS3D_EINVAL;
+  if (idx < 0 || idx >= kProfCount) return OS3D_EINVAL;
   *name = kKernelNames[idx];
   long long n = 0;
   double ms = 0.0, by = 0.0, fl = 0.0;
@@ -792,6 +658,6 @@ int profile_get(int idx, const char** name, long long* launches, double* total_m
   return OS3D_OK;
 }
 
-int profile_count() { return K_COUNT; }
+int profile_count() { return kProfCount; }
 
 }  // namespace os3d

@@ -1,0 +1,398 @@
+// Two-pass 3D DFT of 256^3 volumes (four-step split of the y axis).
+//
+// A 256^3 DFT is six radix-16 stages.  The y axis is split as
+// y = n1 + 16 n2 (input) and ky = 16 k1 + k2 (output):
+//   step A: 16-point DFT over n2 for each n1, then the twiddle w^(n1 k2);
+//   step C: 16-point DFT over n1 for each k2.
+// The natural side (real-space rows, x contiguous) does the x DFT and one
+// y step; the frequency side (tiles of layout4.h) does the other y step and
+// the z DFT.  Each pass reads and writes every value once, so a 3D transform
+// makes one round trip of its intermediate T through memory instead of two.
+//
+// A workgroup is 1024 threads working on four independent sub-problems of
+// 16 x 256 values (four z planes on the natural side, four kx on the
+// frequency side).  Every thread holds 16 values in registers; each pass is
+// three radix-16 DFTs separated by two LDS exchanges.  T is laid out so that
+// both passes move runs of 16 consecutive values (128 bytes):
+//   inverse direction (frequency -> space), written by the frequency side:
+//     T[((k2 * 64 + zb) * 16 + n1) * 1024 + kxb * 16 + zz * 4 + kxx]
+//   forward direction (space -> frequency), written by the natural side:
+//     T[((k2 * 64 + kxb) * 16 + n1) * 1024 + z * 4 + kxx]
+// with z = 4 zb + zz and kx = 4 kxb + kxx.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fft_pass.h"
+#include "layout4.h"
+
+namespace os3d {
+
+constexpr int k4Threads = 1024;
+constexpr int k4LS = 256 + 16 + 1;  // LDS line stride (float2), padded every 16
+constexpr int k4Sub = 16 * k4LS;    // one sub-problem: 16 lines of 256
+
+__device__ __forceinline__ int pad4(int n) { return n + (n >> 4); }
+
+__device__ __forceinline__ float block_sum_1024(float v, float* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  float s = 0.f;
+  if (t == 0)
+    for (int w = 0; w < 16; ++w) s += red[w];
+  return s;
+}
+
+__device__ __forceinline__ void load_twiddles(const PassArgs& a, float2* twl) {
+  for (int i = threadIdx.x; i < 256; i += k4Threads) {
+    float2 v = a.tw[i];
+    if (a.sgn > 0.f) v.y = -v.y;
+    twl[i] = v;
+  }
+}
+
+// Frequency side of the inverse direction: Phi tile (kxb, n1) -> T.
+// z DFT (two stages), then step A over n2 with the twiddle w^(n1 k2).
+template <int LM>
+__global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
+  __shared__ float2 lds[4 * k4Sub];
+  __shared__ float2 twl[256];
+  __shared__ float red[16];
+  const int t = threadIdx.x;
+  const int tile = blockIdx.x, kxb = tile >> 4, n1 = tile & 15;
+  const int j = blockIdx.y;
+  const int g = t & 3, s = (t >> 2) & 15, n2 = t >> 6;
+  load_twiddles(a, twl);
+  const long long base = (long long)tile << 14;
+  float2 v[16];
+  float asum = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = load_elem<LM>(a, j, base + r * 1024 + t, asum);
+  if constexpr (LM == LM_MULBANK) {
+    if (a.partial) {
+      const float tot = block_sum_1024(asum, red);
+      if (t == 0) a.partial[(long long)j * gridDim.x + tile] = tot;
+    }
+  }
+  dft16(v, a.sgn);
+  float2* S = lds + g * k4Sub + n2 * k4LS;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
+  dft16(v, a.sgn);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) S[pad4(s + 16 * r)] = v[r];
+  __syncthreads();
+  const int z = t >> 2, zb = z >> 2, zz = z & 3;
+  float2 u[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) u[q] = lds[g * k4Sub + q * k4LS + pad4(z)];
+  dft16(u, a.sgn);
+#pragma unroll
+  for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[n1 * k2]);
+  float2* T = a.dst_c + (long long)j * a.dst_stride;
+  const long long o = (long long)n1 * 1024 + kxb * 16 + zz * 4 + g;
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) T[((long long)(k2 * 64 + zb) * 16) * 1024 + o] = u[k2];
+}
+
+// Natural side of the inverse direction: T tile (k2, zb) -> rows of four z
+// planes.  Step C over n1, then the x DFT (two stages), then the fused store.
+template <int SM>
+__global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
+  __shared__ float2 lds[4 * k4Sub];
+  __shared__ float2 twl[256];
+  const int t = threadIdx.x;
+  const int tile = blockIdx.x, k2 = tile >> 6, zb = tile & 63;
+  const int j = blockIdx.y;
+  load_twiddles(a, twl);
+  const float2* T = a.src_c + (long long)j * a.src_stride + (long long)tile * 16 * 1024;
+  float2 v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = T[q * 1024 + t];
+  dft16(v, a.sgn);  // over n1 -> k1
+  {
+    const int g = (t >> 2) & 3, kx = (t >> 4) * 4 + (t & 3);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) lds[g * k4Sub + k1 * k4LS + pad4(kx)] = v[k1];
+  }
+  __syncthreads();
+  const int g = t >> 8, k1 = (t >> 4) & 15, s = t & 15;
+  float2* S = lds + g * k4Sub + k1 * k4LS;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+  dft16(v, a.sgn);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
+  dft16(v, a.sgn);
+  const long long row = ((long long)(4 * zb + g) * 256 + (16 * k1 + k2)) * 256;
+  float2 dummy;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) store_elem<SM>(a, j, row + s + 16 * r, v[r], dummy);
+}
+
+// Natural side of the forward direction: rows y = n1 + 16 n2 of four z
+// planes -> T.  x DFT (two stages), then step A over n2 with w^(n1 k2).
+template <int LM>
+__global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
+  __shared__ float2 lds[4 * k4Sub];
+  __shared__ float2 twl[256];
+  const int t = threadIdx.x;
+  const int tile = blockIdx.x, zb = tile >> 4, n1 = tile & 15;
+  const int j = blockIdx.y;
+  load_twiddles(a, twl);
+  const int g = t >> 8, n2 = (t >> 4) & 15, s = t & 15;
+  const long long row = ((long long)(4 * zb + g) * 256 + (n1 + 16 * n2)) * 256;
+  float2 v[16];
+  float asum = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = load_elem<LM>(a, j, row + s + 16 * r, asum);
+  dft16(v, a.sgn);
+  float2* S = lds + g * k4Sub + n2 * k4LS;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
+  dft16(v, a.sgn);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) S[pad4(s + 16 * r)] = v[r];
+  __syncthreads();
+  const int zz = (t >> 2) & 3, kxx = t & 3, kxb = t >> 4, kx = kxb * 4 + kxx;
+  float2 u[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) u[q] = lds[zz * k4Sub + q * k4LS + pad4(kx)];
+  dft16(u, a.sgn);
+#pragma unroll
+  for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[n1 * k2]);
+  float2* T = a.dst_c + (long long)j * a.dst_stride;
+  const long long o = (long long)n1 * 1024 + (4 * zb + zz) * 4 + kxx;
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) T[((long long)(k2 * 64 + kxb) * 16) * 1024 + o] = u[k2];
+}
+
+// Frequency side of the forward direction: T tile (k2, kxb) -> Phi tile
+// (kxb, n1 = k2).  Step C over n1, then the z DFT (two stages), then the
+// fused store (F) or the weighted orientation sum over the pair batch (X).
+template <int SM>
+__global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
+  __shared__ float2 lds[4 * k4Sub];
+  __shared__ float2 twl[256];
+  const int t = threadIdx.x;
+  const int tile = blockIdx.x, k2 = tile >> 6, kxb = tile & 63;
+  load_twiddles(a, twl);
+  const long long pbase = (long long)(kxb * 16 + k2) << 14;
+  const int jb = (SM == SM_ACCUM) ? 0 : blockIdx.y;
+  const int je = (SM == SM_ACCUM) ? a.nb : blockIdx.y + 1;
+  float2 acc[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = make_float2(0.f, 0.f);
+  for (int j = jb; j < je; ++j) {
+    const float2* T = a.src_c + (long long)j * a.src_stride + (long long)tile * 16 * 1024;
+    float2 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = T[q * 1024 + t];
+    dft16(v, a.sgn);  // over n1 -> k1
+    {
+      const int g = t & 3, z = t >> 2;
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) lds[g * k4Sub + k1 * k4LS + pad4(z)] = v[k1];
+    }
+    __syncthreads();
+    const int g = t & 3, s = (t >> 2) & 15, k1 = t >> 6;
+    float2* S = lds + g * k4Sub + k1 * k4LS;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+    dft16(v, a.sgn);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
+    dft16(v, a.sgn);
+    // kz = s + 16 r sits at Phi position pbase + r * 1024 + t
+#pragma unroll
+    for (int r = 0; r < 16; ++r) store_elem<SM>(a, j, pbase + r * 1024 + t, v[r], acc[r]);
+    if constexpr (SM == SM_ACCUM) __syncthreads();
+  }
+  if constexpr (SM == SM_ACCUM) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) accum_flush(a, pbase + r * 1024 + t, acc[r]);
+  }
+}
+
+static int check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return OS3D_EDEVICE;
+  }
+  return OS3D_OK;
+}
+
+static PassArgs base_args(const os3d_bank* b, float sgn) {
+  PassArgs a = {};
+  a.Nz = a.Ny = a.Nx = 256;
+  a.V = b->V;
+  a.N = 256;
+  a.tw = (const float2*)b->d.tw[0];
+  a.sgn = sgn;
+  a.nb = 1;
+  return a;
+}
+
+#define OS3D_LAUNCH4(kernel, kid, alg, a, gy)                                                  \
+  do {                                                                                         \
+    void* tok_ = prof_start(st);                                                               \
+    hipLaunchKernelGGL(kernel, dim3(1024), dim3(k4Threads), 0, st, a);                         \
+    prof_stop(tok_, st, kid, alg, 0.0);                                                        \
+    if ((rc = check(#kernel))) return rc;                                                      \
+  } while (0)
+
+int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, float* scales, void* ws, int nbmax,
+             void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const long long V = b->V;
+  float2* F = (float2*)ws;
+  float2* T = F + V;
+  float* partial = (float*)(T + (long long)nbmax * V);
+  const size_t ubytes = (dtype == OS3D_C64) ? 8 : 4;
+  const bool quant = dtype != OS3D_C64;
+  int rc;
+  for (int bi = 0; bi < batch; ++bi) {
+    {  // F = DFT(f) into the frequency tiles
+      PassArgs a = base_args(b, -1.f);
+      a.src_r = f + (long long)bi * V;
+      a.dst_c = T;
+      OS3D_LAUNCH4((k4_fwd_nat<LM_REAL>), kProfDftFirst, 4.0 * V, a, 1);
+      PassArgs c = base_args(b, -1.f);
+      c.src_c = T;
+      c.dst_c = F;
+      OS3D_LAUNCH4((k4_fwd_phi<SM_C>), kProfDftLast, 0.0, c, 1);
+    }
+    void* Ub = (char*)U + (size_t)bi * b->n_orients * V * ubytes;
+    float* sc = scales ? scales + (long long)bi * b->n_orients : nullptr;
+    for (int r0 = 0; r0 < b->n_unique; r0 += nbmax) {
+      const int nb = std::min(nbmax, b->n_unique - r0);
+      PassArgs z = base_args(b, 1.f);
+      z.nb = nb;
+      double nor = 0.0;
+      for (int jj = 0; jj < nb; ++jj) {
+        const int o = b->rep[r0 + jj];
+        z.rows[jj] = r0 + jj;
+        z.oa[jj] = o;
+        z.ob[jj] = b->partner[o];
+        nor += (z.ob[jj] >= 0) ? 2.0 : 1.0;
+      }
+      z.src_c = F;
+      z.psi = b->d.psi;
+      z.dst_c = T;
+      z.dst_stride = V;
+      z.partial = quant ? partial : nullptr;
+      {
+        void* tok = prof_start(st);
+        hipLaunchKernelGGL((k4_inv_phi<LM_MULBANK>), dim3(1024, nb), dim3(k4Threads), 0, st, z);
+        prof_stop(tok, st, kProfFwdFirst, 0.0, 0.0);
+        if ((rc = check("k4_inv_phi"))) return rc;
+      }
+      if (quant) {
+        void* tok = prof_start(st);
+        launch_scales(partial, 1024, z, dtype, sc, nb, st);
+        prof_stop(tok, st, kProfScales, 0.0, 0.0);
+        if ((rc = check("k_scales"))) return rc;
+      }
+      PassArgs x = z;
+      x.partial = nullptr;
+      x.src_c = T;
+      x.src_stride = V;
+      x.Uout = Ub;
+      x.dtype = dtype;
+      x.scales = quant ? sc : nullptr;
+      x.out_scale = 1.f / (float)V;
+      {
+        void* tok = prof_start(st);
+        hipLaunchKernelGGL((k4_inv_nat<SM_UOUT>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        prof_stop(tok, st, kProfFwdLast, nor * (double)V * (double)ubytes, 0.0);
+        if ((rc = check("k4_inv_nat"))) return rc;
+      }
+    }
+  }
+  return OS3D_OK;
+}
+
+int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out, void* ws,
+            bool divide_M, int nbmax, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const long long V = b->V;
+  float2* X = (float2*)ws;
+  float2* T = X + V;
+  const size_t ubytes = (dtype == OS3D_C64) ? 8 : 4;
+  int rc;
+  for (int bi = 0; bi < batch; ++bi) {
+    const void* Ub = (const char*)U + (size_t)bi * b->n_orients * V * ubytes;
+    const float* sc = scales ? scales + (long long)bi * b->n_orients : nullptr;
+    for (int r0 = 0; r0 < b->n_unique; r0 += nbmax) {
+      const int nb = std::min(nbmax, b->n_unique - r0);
+      PassArgs x = base_args(b, -1.f);
+      x.nb = nb;
+      double nor = 0.0;
+      for (int jj = 0; jj < nb; ++jj) {
+        const int o = b->rep[r0 + jj];
+        x.rows[jj] = r0 + jj;
+        x.oa[jj] = o;
+        x.ob[jj] = b->partner[o];
+        nor += (x.ob[jj] >= 0) ? 2.0 : 1.0;
+      }
+      x.U = Ub;
+      x.dtype = dtype;
+      x.scales = (dtype == OS3D_C64) ? nullptr : sc;
+      x.dst_c = T;
+      x.dst_stride = V;
+      {
+        void* tok = prof_start(st);
+        hipLaunchKernelGGL((k4_fwd_nat<LM_UIN>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        prof_stop(tok, st, kProfRecFirst, nor * (double)V * (double)ubytes, 0.0);
+        if ((rc = check("k4_fwd_nat"))) return rc;
+      }
+      PassArgs z = x;
+      z.src_c = T;
+      z.src_stride = V;
+      z.psi = b->d.psi;
+      z.dst_c = X;
+      z.accumulate = (r0 > 0) ? 1 : 0;
+      OS3D_LAUNCH4((k4_fwd_phi<SM_ACCUM>), kProfRecLast, 0.0, z, 1);
+    }
+    PassArgs z = base_args(b, 1.f);
+    z.src_c = X;
+    z.M = b->d.M;
+    z.eps = (float)b->params.eps;
+    z.divide = divide_M ? 1 : 0;
+    z.dst_c = T;
+    OS3D_LAUNCH4((k4_inv_phi<LM_DIVM>), kProfInvFirst, 0.0, z, 1);
+    PassArgs x = base_args(b, 1.f);
+    x.src_c = T;
+    x.dst_r = f_out + (long long)bi * V;
+    x.out_scale = 1.f / (float)V;
+    OS3D_LAUNCH4((k4_inv_nat<SM_REAL>), kProfInvLast, 4.0 * V, x, 1);
+  }
+  return OS3D_OK;
+}
+
+}  // namespace os3d

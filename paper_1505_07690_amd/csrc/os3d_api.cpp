@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -175,6 +176,10 @@ os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_
   make_rows(orients, n, b->partner, b->rep, b->row_of, b->conj_of, b->paired);
   b->n_unique = (int)b->rep.size();
   b->Npad = (b->n_unique + 15) / 16 * 16;
+  // 256^3 volumes take the two-pass transform and its frequency tiles
+  b->layout = (dims[0] == 256 && dims[1] == 256 && dims[2] == 256) ? 1 : 0;
+  if (const char* e = std::getenv("OS3D_THREE_PASS"))
+    if (e[0] == '1') b->layout = 0;
   const BankLayout lay = layout(dims, b->n_unique, p->L);
   if (bank_bytes_given < lay.total) {
     delete b;

@@ -82,6 +82,7 @@ struct os3d_bank {
   int n_orients;
   int n_unique;
   int paired;
+  int layout;                 // frequency storage order: 0 natural, 1 four-step tiles of 256^3
   int L;
   int Npad;
   int K;

@@ -1,0 +1,192 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration that
+bench.py times (the two-pass 256^3 path and the three-pass 128^3 path).
+
+* 256^3 with the 12 icosahedron orientations: everything against the FP64
+  oracle (bank, M, kappa, forward, adjoint, reconstruction, 16-bit storage).
+* 128^3 x 42 orientations, L = 16 (the mid-size workload): everything against
+  the oracle.
+* 256^3 x 162 orientations, L = 24 (the headline workload): the bank rows and
+  whole score volumes of sampled orientations against the oracle (up to the
+  normaliser kappa, which the oracle would need all 162 rows at full size to
+  form), plus properties that hold at any size: the band mean of M is 1,
+  exact reconstruction of band-limited volumes, the adjoint identity,
+  antipodal conjugacy and determinism.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1505_07690_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    from paper_1505_07690_amd import os3d
+    os3d.lib()
+    return t
+
+
+def _params(L, n):
+    return O.WaveletParams(L=L, s_theta=inputs.s_theta_for(n))
+
+
+def _complex_scores(No, shape, seed):
+    rng = np.random.default_rng(seed)
+    U = np.empty((No,) + shape, dtype=np.complex64)
+    for i in range(No):
+        U[i].real = rng.standard_normal(shape, dtype=np.float32)
+        U[i].imag = rng.standard_normal(shape, dtype=np.float32)
+    return U
+
+
+@pytest.mark.parametrize("shape,level,L", [((256, 256, 256), 0, 4), ((128, 128, 128), 1, 16)],
+                         ids=["256cube_No12_L4", "128cube_No42_L16"])
+def test_full_size_against_oracle(torch, shape, level, L):
+    from paper_1505_07690_amd import os3d
+    n = inputs.icosahedral_orientations(level)
+    p = _params(L, len(n))
+    vol = inputs.tubes(shape, 12, (1.0, 3.0), 0.2, 5 if level else 0, 21)
+    ob = O.build_bank(shape, n, p)
+    gb = os3d.Bank(shape, n, p)
+    if shape == (256, 256, 256):
+        from paper_1505_07690_amd.os3d import lib  # noqa: F401
+    psi = np.stack([gb.psi(i).cpu().numpy() for i in range(len(n))])
+    assert rel(psi, ob["psi_hat"]) < TOL
+    assert rel(gb.M().cpu().numpy(), ob["M"]) < TOL
+    assert abs(gb.kappa - ob["kappa"]) < 1e-6 * ob["kappa"]
+    del psi
+    f = torch.from_numpy(vol).cuda()
+    U, _ = os3d.forward(f, gb)
+    Uo = O.forward(vol.astype(np.float64), ob)
+    assert rel(U.cpu().numpy(), Uo) < TOL
+    del U
+    # reconstruction and adjoint of a general complex score
+    Ur = _complex_scores(len(n), shape, 5)
+    Ug = torch.from_numpy(Ur).cuda()
+    rec = os3d.reconstruct(Ug, gb).cpu().numpy()
+    adj = os3d.adjoint(Ug, gb).cpu().numpy()
+    del Ug
+    X = O.os3d_oracle._orientation_sum(Ur.astype(np.complex128), ob)
+    assert rel(rec, np.real(O.idft3(X / np.maximum(ob["M"], p.eps)))) < TOL
+    assert rel(adj, np.real(O.idft3(X))) < TOL
+    del X, Ur
+    # 16-bit score storage on the same path
+    for fmt, bound in (("bf16", 4e-3), ("fp16", 5e-4)):
+        Uq, sc = os3d.forward(f, gb, dtype=fmt)
+        assert rel(os3d.unpack16(Uq, sc, fmt).cpu().numpy(), Uo) < bound
+        rq = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
+        assert rel(rq, O.reconstruct(Uo, ob)) < bound
+        del Uq
+
+
+@pytest.fixture(scope="module")
+def headline(torch):
+    """The 256^3 x 162, L = 24 workload on the GPU."""
+    from paper_1505_07690_amd import os3d
+    c = inputs.CONFIGS["C"]
+    n = inputs.icosahedral_orientations(c["level"])
+    p = _params(c["L"], len(n))
+    gb = os3d.Bank(c["shape"], n, p)
+    vol = inputs.config_volume("C")
+    return dict(n=n, p=p, gb=gb, vol=vol, shape=c["shape"])
+
+
+def test_headline_bank_rows_sampled(headline):
+    """Bank rows of sampled orientations (both members of a pair) over the
+    whole grid against the oracle's g h (kappa divided out)."""
+    n, p, gb, shape = headline["n"], headline["p"], headline["gb"], headline["shape"]
+    a = O.cake_coeffs(O.sh_coeffs_A(p))
+    wz, wy, wx, nyq = O.freq_grid(shape)
+    d = np.linalg.norm(n[:, None] + n[None], axis=2)
+    partner = np.argmin(d, axis=1)
+    for i in (0, int(partner[0]), 77, 161):
+        raw = O.bank_values(wz, wy, wx, nyq, n[i:i + 1], a, p)[0]
+        assert rel(gb.psi(i).cpu().numpy() / gb.kappa, raw) < TOL, i
+
+
+def test_headline_M_band_mean_is_one(headline):
+    gb, shape = headline["gb"], headline["shape"]
+    M = gb.M().cpu().numpy().astype(np.float64)
+    wz, wy, wx, nyq = O.freq_grid(shape)
+    rho = np.sqrt(wx ** 2 + wy ** 2 + wz ** 2)
+    band = (rho > 0) & (rho <= np.pi / 2) & ~nyq
+    assert abs(M[band].mean() - 1.0) < 1e-6
+    # admissibility (Eq. 4) away from the Nyquist frequency
+    assert M[(rho <= 0.8 * np.pi) & ~nyq].min() > 0.05
+    # M is even
+    S = np.roll(np.flip(M, axis=(0, 1, 2)), 1, axis=(0, 1, 2))
+    assert np.max(np.abs(S - M)) <= 1e-6 * M.max()
+
+
+def test_headline_scores_sampled(torch, headline):
+    """Whole score volumes of sampled orientations against the oracle's
+    IDFT(g h DFT(f)) (kappa divided out); antipodal partner exactly conjugate."""
+    from paper_1505_07690_amd import os3d
+    n, p, gb, shape, vol = headline["n"], headline["p"], headline["gb"], headline["shape"], headline["vol"]
+    f = torch.from_numpy(vol).cuda()
+    U, _ = os3d.forward(f, gb)
+    U2, _ = os3d.forward(f, gb)
+    assert torch.equal(U, U2)  # deterministic
+    del U2
+    a = O.cake_coeffs(O.sh_coeffs_A(p))
+    wz, wy, wx, nyq = O.freq_grid(shape)
+    F = O.dft3(vol.astype(np.float64))
+    d = np.linalg.norm(n[:, None] + n[None], axis=2)
+    partner = np.argmin(d, axis=1)
+    for i in (3, 100):
+        raw = O.bank_values(wz, wy, wx, nyq, n[i:i + 1], a, p)[0]
+        want = O.idft3(raw * F)
+        got = U[i].cpu().numpy() / gb.kappa
+        assert rel(got, want) < TOL, i
+        assert torch.equal(U[int(partner[i])], torch.conj(U[i]).resolve_conj())
+
+
+def test_headline_exact_reconstruction_and_adjoint_identity(torch, headline):
+    from paper_1505_07690_amd import os3d
+    gb, shape = headline["gb"], headline["shape"]
+    fbl = inputs.bandlimited(shape, 0.75, seed=8)
+    f = torch.from_numpy(fbl).cuda()
+    U, _ = os3d.forward(f, gb)
+    rec = os3d.reconstruct(U, gb).cpu().numpy()
+    assert rel(rec, fbl) < TOL
+    # <W f, V> = <f, W* V> for a random complex V (FP64 sums of FP32 products)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    Vr = torch.randn(U.shape, dtype=torch.complex64, device="cuda", generator=g)
+    lhs = torch.sum((U.conj() * Vr).real.double()).item()
+    rhs = torch.sum(f.double() * os3d.adjoint(Vr, gb).double()).item()
+    assert abs(lhs - rhs) < 1e-5 * abs(rhs)
+
+
+def test_headline_adjoint_of_one_pair_against_oracle(torch, headline):
+    """W* of a score supported on one antipodal pair, over the whole grid,
+    against the oracle (kappa divided out)."""
+    from paper_1505_07690_amd import os3d
+    n, p, gb, shape = headline["n"], headline["p"], headline["gb"], headline["shape"]
+    d = np.linalg.norm(n[:, None] + n[None], axis=2)
+    partner = np.argmin(d, axis=1)
+    i, j = 10, int(partner[10])
+    rng = np.random.default_rng(9)
+    Ui = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    Uj = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    Ug = torch.zeros((len(n),) + shape, dtype=torch.complex64, device="cuda")
+    Ug[i] = torch.from_numpy(Ui).cuda()
+    Ug[j] = torch.from_numpy(Uj).cuda()
+    adj = os3d.adjoint(Ug, gb).cpu().numpy() / gb.kappa
+    del Ug
+    a = O.cake_coeffs(O.sh_coeffs_A(p))
+    wz, wy, wx, nyq = O.freq_grid(shape)
+    X = np.zeros(shape, dtype=np.complex128)
+    for k, Uk in ((i, Ui), (j, Uj)):
+        raw = O.bank_values(wz, wy, wx, nyq, n[k:k + 1], a, p)[0]
+        X += raw * O.dft3(Uk.astype(np.complex128))
+    assert rel(adj, np.real(O.idft3(X))) < TOL
