@@ -61,42 +61,52 @@ __device__ __forceinline__ long long gaddr(const PassArgs& a, long long line, in
 
 __device__ __forceinline__ int lidx(int LS, int w, int n) { return w * LS + n + (n >> 4); }
 
-__device__ __forceinline__ float2 load_score(const void* U, int dtype, long long i, float s) {
-  if (dtype == OS3D_C64) return ((const float2*)U)[i];
-  const unsigned int q = ((const unsigned int*)U)[i];
-  float re, im;
-  if (dtype == OS3D_F16X2) {
-    re = __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
-    im = __half2float(__ushort_as_half((unsigned short)(q >> 16)));
-  } else {
-    re = __uint_as_float((q & 0xffffu) << 16);
-    im = __uint_as_float(q & 0xffff0000u);
-  }
-  return make_float2(re * s, im * s);
-}
-
 __device__ __forceinline__ unsigned int bf16_rne(float x) {
   unsigned int u = __float_as_uint(x);
   unsigned int lsb = (u >> 16) & 1u;
   return (u + 0x7fffu + lsb) >> 16;
 }
 
-__device__ __forceinline__ void store_score(void* U, int dtype, long long i, float2 v, float inv_s) {
-  if (dtype == OS3D_C64) {
-    ((float2*)U)[i] = v;
-    return;
+// Score element i as complex float (16-bit pairs times their scale s).  The
+// storage type is a template parameter so that the loads of a pass are not
+// separated by branches and can all be in flight together.
+template <int DT>
+__device__ __forceinline__ float2 load_score(const void* U, long long i, float s) {
+  if constexpr (DT == OS3D_C64) {
+    return ((const float2*)U)[i];
+  } else {
+    const unsigned int q = ((const unsigned int*)U)[i];
+    float re, im;
+    if constexpr (DT == OS3D_F16X2) {
+      re = __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
+      im = __half2float(__ushort_as_half((unsigned short)(q >> 16)));
+    } else {
+      re = __uint_as_float((q & 0xffffu) << 16);
+      im = __uint_as_float(q & 0xffff0000u);
+    }
+    return make_float2(re * s, im * s);
   }
-  float re = v.x * inv_s, im = v.y * inv_s;
-  unsigned int q;
-  if (dtype == OS3D_F16X2)
-    q = (unsigned int)__half_as_ushort(__float2half_rn(re)) | ((unsigned int)__half_as_ushort(__float2half_rn(im)) << 16);
-  else
-    q = bf16_rne(re) | (bf16_rne(im) << 16);
-  ((unsigned int*)U)[i] = q;
+}
+
+
+template <int DT>
+__device__ __forceinline__ void store_score(void* U, long long i, float2 v, float inv_s) {
+  if constexpr (DT == OS3D_C64) {
+    ((float2*)U)[i] = v;
+  } else {
+    const float re = v.x * inv_s, im = v.y * inv_s;
+    unsigned int q;
+    if constexpr (DT == OS3D_F16X2)
+      q = (unsigned int)__half_as_ushort(__float2half_rn(re)) |
+          ((unsigned int)__half_as_ushort(__float2half_rn(im)) << 16);
+    else
+      q = bf16_rne(re) | (bf16_rne(im) << 16);
+    ((unsigned int*)U)[i] = q;
+  }
 }
 
 // Fused first-pass load of element g (line position) for pair slot j.
-template <int LM>
+template <int LM, int DT = OS3D_C64>
 __device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long g, float& asum) {
   if constexpr (LM == LM_REAL) {
     return make_float2(a.src_r[g], 0.f);
@@ -110,10 +120,10 @@ __device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long 
   } else if constexpr (LM == LM_UIN) {
     const int ia = a.oa[j], ib = a.ob[j];
     const float sa = a.scales ? a.scales[ia] : 1.f;
-    float2 v = load_score(a.U, a.dtype, (long long)ia * a.V + g, sa);
+    float2 v = load_score<DT>(a.U, (long long)ia * a.V + g, sa);
     if (ib >= 0) {
       const float sb = a.scales ? a.scales[ib] : 1.f;
-      v = cadd(v, cconj(load_score(a.U, a.dtype, (long long)ib * a.V + g, sb)));
+      v = cadd(v, cconj(load_score<DT>(a.U, (long long)ib * a.V + g, sb)));
     }
     return v;
   } else {  // LM_DIVM
@@ -124,7 +134,7 @@ __device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long 
 }
 
 // Fused last-pass store of element g for pair slot j (SM_ACCUM adds into acc).
-template <int SM>
+template <int SM, int DT = OS3D_C64>
 __device__ __forceinline__ void store_elem(const PassArgs& a, int j, long long g, float2 v, float2& acc) {
   if constexpr (SM == SM_C) {
     a.dst_c[j * a.dst_stride + g] = v;
@@ -132,8 +142,8 @@ __device__ __forceinline__ void store_elem(const PassArgs& a, int j, long long g
     const float2 u = cscale(v, a.out_scale);
     const int ia = a.oa[j], ib = a.ob[j];
     const float inv_s = a.scales ? 1.f / a.scales[ia] : 1.f;
-    store_score(a.Uout, a.dtype, (long long)ia * a.V + g, u, inv_s);
-    if (ib >= 0) store_score(a.Uout, a.dtype, (long long)ib * a.V + g, cconj(u), inv_s);
+    store_score<DT>(a.Uout, (long long)ia * a.V + g, u, inv_s);
+    if (ib >= 0) store_score<DT>(a.Uout, (long long)ib * a.V + g, cconj(u), inv_s);
   } else if constexpr (SM == SM_ACCUM) {
     const float p = a.psi[(long long)a.rows[j] * a.V + g];
     acc = make_float2(acc.x + p * v.x, acc.y + p * v.y);

@@ -54,7 +54,7 @@ __device__ __forceinline__ void stage(const PassArgs& a, const float2* __restric
   }
 }
 
-template <int LM, int SM>
+template <int LM, int SM, int DT>
 __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a) {
   extern __shared__ float2 lds[];
   __shared__ float red[kThreads];
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a) {
         }
         if (w < nl) {
           const long long g = gaddr(a, line0 + w, n);
-          const float2 v = load_elem<LM>(a, j, g, asum);
+          const float2 v = load_elem<LM, DT>(a, j, g, asum);
           buf0[lidx(a.LS, w, n)] = v;
         }
       }
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_pass(PassArgs a) {
         }
         if (w < nl) {
           const long long g = gaddr(a, line0 + w, n);
-          store_elem<SM>(a, j, g, cur[lidx(a.LS, w, n)], acc[e]);
+          store_elem<SM, DT>(a, j, g, cur[lidx(a.LS, w, n)], acc[e]);
         }
       }
     }
@@ -207,7 +207,7 @@ __device__ __forceinline__ long long gaddr_t(const PassArgs& a, long long line, 
   }
 }
 
-template <int N, int AXIS, int LM, int SM>
+template <int N, int AXIS, int LM, int SM, int DT>
 __global__ __launch_bounds__(kThreads) void k_fast(PassArgs a) {
   using C = FastCfg<N>;
   __shared__ float2 buf[C::W * C::LS];
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_fast(PassArgs a) {
     float asum = 0.f;
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-      v[r] = valid ? load_elem<LM>(a, j, gaddr_t<N, AXIS>(a, line, s + C::TL * r), asum) : make_float2(0.f, 0.f);
+      v[r] = valid ? load_elem<LM, DT>(a, j, gaddr_t<N, AXIS>(a, line, s + C::TL * r), asum) : make_float2(0.f, 0.f);
     if constexpr (LM == LM_MULBANK) {
       if (a.partial) {
         red[t] = asum;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_fast(PassArgs a) {
       dft_r<C::R2>(u, a.sgn);
       if (valid) {
 #pragma unroll
-        for (int r = 0; r < C::R2; ++r) store_elem<SM>(a, j, gaddr_t<N, AXIS>(a, line, jj + 16 * r), u[r], acc[q * C::R2 + r]);
+        for (int r = 0; r < C::R2; ++r) store_elem<SM, DT>(a, j, gaddr_t<N, AXIS>(a, line, jj + 16 * r), u[r], acc[q * C::R2 + r]);
       }
     }
     __syncthreads();
@@ -391,36 +391,52 @@ void prof_stop(void* token, void* stream, int kid, double alg_bytes, double alg_
   delete r;
 }
 
-template <int LM, int SM, int N, int AXIS>
+template <int LM, int SM, int N, int AXIS, int DT>
 static void launch_fast(const PassArgs& a, int grid_y, hipStream_t st) {
   const long long tiles = (a.lines + FastCfg<N>::W - 1) / FastCfg<N>::W;
-  hipLaunchKernelGGL((k_fast<N, AXIS, LM, SM>), dim3((unsigned)tiles, grid_y), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL((k_fast<N, AXIS, LM, SM, DT>), dim3((unsigned)tiles, grid_y), dim3(kThreads), 0, st, a);
 }
 
-template <int LM, int SM, int N>
+template <int LM, int SM, int N, int DT>
 static void launch_fast_axis(const PassArgs& a, int grid_y, hipStream_t st) {
-  if (a.axis == 0) launch_fast<LM, SM, N, 0>(a, grid_y, st);
-  else if (a.axis == 1) launch_fast<LM, SM, N, 1>(a, grid_y, st);
-  else launch_fast<LM, SM, N, 2>(a, grid_y, st);
+  if constexpr (LM == LM_UIN || SM == SM_UOUT) {
+    launch_fast<LM, SM, N, 2, DT>(a, grid_y, st);  // scores are read and written along x only
+  } else {
+    if (a.axis == 0) launch_fast<LM, SM, N, 0, DT>(a, grid_y, st);
+    else if (a.axis == 1) launch_fast<LM, SM, N, 1, DT>(a, grid_y, st);
+    else launch_fast<LM, SM, N, 2, DT>(a, grid_y, st);
+  }
+}
+
+template <int LM, int SM, int DT>
+static void launch_pass_dt(const PassArgs& a, int grid_y, hipStream_t st) {
+  if (a.N == 256) {
+    launch_fast_axis<LM, SM, 256, DT>(a, grid_y, st);
+  } else if (a.N == 128) {
+    launch_fast_axis<LM, SM, 128, DT>(a, grid_y, st);
+  } else if (a.N == 64) {
+    launch_fast_axis<LM, SM, 64, DT>(a, grid_y, st);
+  } else {
+    const long long tiles = (a.lines + a.W - 1) / a.W;
+    static bool attr_set = false;
+    if (!attr_set) {
+      (void)hipFuncSetAttribute((const void*)k_pass<LM, SM, DT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                96 * 1024);
+      attr_set = true;
+    }
+    hipLaunchKernelGGL((k_pass<LM, SM, DT>), dim3((unsigned)tiles, grid_y), dim3(kThreads), pass_lds(a), st, a);
+  }
 }
 
 template <int LM, int SM>
 static int run_pass(int kid, double alg, const PassArgs& a, int grid_y, hipStream_t st) {
   void* tok = prof_start(st);
-  if (a.N == 256) {
-    launch_fast_axis<LM, SM, 256>(a, grid_y, st);
-  } else if (a.N == 128) {
-    launch_fast_axis<LM, SM, 128>(a, grid_y, st);
-  } else if (a.N == 64) {
-    launch_fast_axis<LM, SM, 64>(a, grid_y, st);
+  if constexpr (LM == LM_UIN || SM == SM_UOUT) {
+    if (a.dtype == OS3D_BF16X2) launch_pass_dt<LM, SM, OS3D_BF16X2>(a, grid_y, st);
+    else if (a.dtype == OS3D_F16X2) launch_pass_dt<LM, SM, OS3D_F16X2>(a, grid_y, st);
+    else launch_pass_dt<LM, SM, OS3D_C64>(a, grid_y, st);
   } else {
-    const long long tiles = (a.lines + a.W - 1) / a.W;
-    static bool attr_set = false;
-    if (!attr_set) {
-      (void)hipFuncSetAttribute((const void*)k_pass<LM, SM>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-      attr_set = true;
-    }
-    hipLaunchKernelGGL((k_pass<LM, SM>), dim3((unsigned)tiles, grid_y), dim3(kThreads), pass_lds(a), st, a);
+    launch_pass_dt<LM, SM, OS3D_C64>(a, grid_y, st);
   }
   prof_stop(tok, st, kid, alg, 0.0);
   return check_launch(kKernelNames[kid]);
@@ -434,8 +450,11 @@ static double score_bytes(const os3d_bank* b, const PassArgs& a, int nb, size_t 
   return (double)n * (double)b->V * (double)ubytes;
 }
 
+// Orientation pairs per launch: larger batches amortise the spectrum loads
+// and the orientation-sum read-modify-write and keep more workgroups in
+// flight; each pair costs one intermediate volume of workspace.
 static int pair_batch(const os3d_bank* b) {
-  int nb = 8;
+  int nb = kMaxBatch;
   if (const char* e = getenv("OS3D_PAIR_BATCH")) nb = atoi(e);
   return std::max(1, std::min(std::min(nb, kMaxBatch), b->n_unique));
 }

@@ -30,7 +30,9 @@ namespace os3d {
 
 constexpr int k4Threads = 1024;
 constexpr int k4LS = 256 + 16 + 1;  // LDS line stride (float2), padded every 16
-constexpr int k4Sub = 16 * k4LS;    // one sub-problem: 16 lines of 256
+constexpr int k4Sub = 16 * k4LS + 4;  // one sub-problem: 16 lines of 256; the extra 4 values shift
+                                     // successive sub-problems by 8 banks, so lanes that interleave
+                                     // sub-problems hit distinct banks
 
 __device__ __forceinline__ int pad4(int n) { return n + (n >> 4); }
 
@@ -54,57 +56,87 @@ __device__ __forceinline__ void load_twiddles(const PassArgs& a, float2* twl) {
 }
 
 // Frequency side of the inverse direction: Phi tile (kxb, n1) -> T.
-// z DFT (two stages), then step A over n2 with the twiddle w^(n1 k2).
+// The spectrum tile (F, or X / max(M, eps)) is loaded once for the pair
+// batch of the launch; per pair: multiply by the bank row (the next row is
+// prefetched while the current pair is transformed), z DFT (two stages),
+// step A over n2 and the twiddle w^(n1 k2).  Consecutive workgroups take
+// consecutive kxb, so the 128-byte runs they write into T are adjacent.
 template <int LM>
 __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
   __shared__ float red[16];
   const int t = threadIdx.x;
-  const int tile = blockIdx.x, kxb = tile >> 4, n1 = tile & 15;
-  const int j = blockIdx.y;
+  const int kxb = blockIdx.x & 63, n1 = blockIdx.x >> 6, tile = kxb * 16 + n1;
   const int g = t & 3, s = (t >> 2) & 15, n2 = t >> 6;
   load_twiddles(a, twl);
   const long long base = (long long)tile << 14;
-  float2 v[16];
-  float asum = 0.f;
+  float2 spec[16];
+  {
+    float unused = 0.f;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = load_elem<LM>(a, j, base + r * 1024 + t, asum);
-  if constexpr (LM == LM_MULBANK) {
-    if (a.partial) {
-      const float tot = block_sum_1024(asum, red);
-      if (t == 0) a.partial[(long long)j * gridDim.x + tile] = tot;
-    }
+    for (int r = 0; r < 16; ++r)
+      spec[r] = load_elem<(LM == LM_MULBANK) ? LM_C : LM>(a, 0, base + r * 1024 + t, unused);
   }
-  dft16(v, a.sgn);
-  float2* S = lds + g * k4Sub + n2 * k4LS;
+  float pnx[16];
+  if constexpr (LM == LM_MULBANK) {
+    const float* prow = a.psi + (long long)a.rows[0] * a.V + base + t;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
-#pragma unroll
-  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
-  dft16(v, a.sgn);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) S[pad4(s + 16 * r)] = v[r];
-  __syncthreads();
+    for (int r = 0; r < 16; ++r) pnx[r] = prow[r * 1024];
+  }
   const int z = t >> 2, zb = z >> 2, zz = z & 3;
-  float2 u[16];
+  for (int j = 0; j < a.nb; ++j) {
+    float2 v[16];
+    if constexpr (LM == LM_MULBANK) {
+      float asum = 0.f;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) u[q] = lds[g * k4Sub + q * k4LS + pad4(z)];
-  dft16(u, a.sgn);
+      for (int r = 0; r < 16; ++r) {
+        v[r] = cscale(spec[r], pnx[r]);
+        asum += sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
+      }
+      if (j + 1 < a.nb) {
+        const float* prow = a.psi + (long long)a.rows[j + 1] * a.V + base + t;
 #pragma unroll
-  for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[n1 * k2]);
-  float2* T = a.dst_c + (long long)j * a.dst_stride;
-  const long long o = (long long)n1 * 1024 + kxb * 16 + zz * 4 + g;
+        for (int r = 0; r < 16; ++r) pnx[r] = prow[r * 1024];
+      }
+      if (a.partial) {
+        const float tot = block_sum_1024(asum, red);
+        if (t == 0) a.partial[(long long)j * gridDim.x + blockIdx.x] = tot;
+      }
+    } else {
 #pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) T[((long long)(k2 * 64 + zb) * 16) * 1024 + o] = u[k2];
+      for (int r = 0; r < 16; ++r) v[r] = spec[r];
+    }
+    dft16(v, a.sgn);
+    float2* S = lds + g * k4Sub + n2 * k4LS;
+    if (j > 0) __syncthreads();  // the previous pair's step-A reads are done
+#pragma unroll
+    for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+#pragma unroll
+    for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
+    dft16(v, a.sgn);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) S[pad4(s + 16 * r)] = v[r];
+    __syncthreads();
+    float2 u[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) u[q] = lds[g * k4Sub + q * k4LS + pad4(z)];
+    dft16(u, a.sgn);
+#pragma unroll
+    for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[n1 * k2]);
+    float2* T = a.dst_c + (long long)j * a.dst_stride;
+    const long long o = (long long)n1 * 1024 + kxb * 16 + zz * 4 + g;
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) T[((long long)(k2 * 64 + zb) * 16) * 1024 + o] = u[k2];
+  }
 }
 
 // Natural side of the inverse direction: T tile (k2, zb) -> rows of four z
 // planes.  Step C over n1, then the x DFT (two stages), then the fused store.
-template <int SM>
+template <int SM, int DT>
 __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
@@ -140,17 +172,19 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
   const long long row = ((long long)(4 * zb + g) * 256 + (16 * k1 + k2)) * 256;
   float2 dummy;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) store_elem<SM>(a, j, row + s + 16 * r, v[r], dummy);
+  for (int r = 0; r < 16; ++r) store_elem<SM, DT>(a, j, row + s + 16 * r, v[r], dummy);
 }
 
 // Natural side of the forward direction: rows y = n1 + 16 n2 of four z
 // planes -> T.  x DFT (two stages), then step A over n2 with w^(n1 k2).
-template <int LM>
+// Consecutive workgroups take consecutive n1: sixteen of them read all 256
+// rows of the same four planes.
+template <int LM, int DT>
 __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
   const int t = threadIdx.x;
-  const int tile = blockIdx.x, zb = tile >> 4, n1 = tile & 15;
+  const int zb = blockIdx.x >> 4, n1 = blockIdx.x & 15;
   const int j = blockIdx.y;
   load_twiddles(a, twl);
   const int g = t >> 8, n2 = (t >> 4) & 15, s = t & 15;
@@ -158,7 +192,7 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
   float2 v[16];
   float asum = 0.f;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = load_elem<LM>(a, j, row + s + 16 * r, asum);
+  for (int r = 0; r < 16; ++r) v[r] = load_elem<LM, DT>(a, j, row + s + 16 * r, asum);
   dft16(v, a.sgn);
   float2* S = lds + g * k4Sub + n2 * k4LS;
 #pragma unroll
@@ -281,7 +315,7 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
       PassArgs a = base_args(b, -1.f);
       a.src_r = f + (long long)bi * V;
       a.dst_c = T;
-      OS3D_LAUNCH4((k4_fwd_nat<LM_REAL>), kProfDftFirst, 4.0 * V, a, 1);
+      OS3D_LAUNCH4((k4_fwd_nat<LM_REAL, OS3D_C64>), kProfDftFirst, 4.0 * V, a, 1);
       PassArgs c = base_args(b, -1.f);
       c.src_c = T;
       c.dst_c = F;
@@ -308,7 +342,7 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
       z.partial = quant ? partial : nullptr;
       {
         void* tok = prof_start(st);
-        hipLaunchKernelGGL((k4_inv_phi<LM_MULBANK>), dim3(1024, nb), dim3(k4Threads), 0, st, z);
+        hipLaunchKernelGGL((k4_inv_phi<LM_MULBANK>), dim3(1024), dim3(k4Threads), 0, st, z);
         prof_stop(tok, st, kProfFwdFirst, 0.0, 0.0);
         if ((rc = check("k4_inv_phi"))) return rc;
       }
@@ -328,7 +362,12 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
       x.out_scale = 1.f / (float)V;
       {
         void* tok = prof_start(st);
-        hipLaunchKernelGGL((k4_inv_nat<SM_UOUT>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        if (dtype == OS3D_C64)
+          hipLaunchKernelGGL((k4_inv_nat<SM_UOUT, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        else if (dtype == OS3D_BF16X2)
+          hipLaunchKernelGGL((k4_inv_nat<SM_UOUT, OS3D_BF16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        else
+          hipLaunchKernelGGL((k4_inv_nat<SM_UOUT, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfFwdLast, nor * (double)V * (double)ubytes, 0.0);
         if ((rc = check("k4_inv_nat"))) return rc;
       }
@@ -367,7 +406,12 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
       x.dst_stride = V;
       {
         void* tok = prof_start(st);
-        hipLaunchKernelGGL((k4_fwd_nat<LM_UIN>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        if (dtype == OS3D_C64)
+          hipLaunchKernelGGL((k4_fwd_nat<LM_UIN, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        else if (dtype == OS3D_BF16X2)
+          hipLaunchKernelGGL((k4_fwd_nat<LM_UIN, OS3D_BF16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        else
+          hipLaunchKernelGGL((k4_fwd_nat<LM_UIN, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfRecFirst, nor * (double)V * (double)ubytes, 0.0);
         if ((rc = check("k4_fwd_nat"))) return rc;
       }
@@ -390,7 +434,7 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
     x.src_c = T;
     x.dst_r = f_out + (long long)bi * V;
     x.out_scale = 1.f / (float)V;
-    OS3D_LAUNCH4((k4_inv_nat<SM_REAL>), kProfInvLast, 4.0 * V, x, 1);
+    OS3D_LAUNCH4((k4_inv_nat<SM_REAL, OS3D_C64>), kProfInvLast, 4.0 * V, x, 1);
   }
   return OS3D_OK;
 }
