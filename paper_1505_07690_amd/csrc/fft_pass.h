@@ -159,6 +159,111 @@ __device__ __forceinline__ void accum_flush(const PassArgs& a, long long g, floa
 }
 
 
+// K values of one thread at the affine positions g0 + r d (r < K), for pair
+// slot j.  Uniform conditions (partner present, division, scales) are
+// decided once, outside the unrolled loops, so that each group of loads sits
+// in one basic block and is issued back to back.
+template <int LM, int DT, int K>
+__device__ __forceinline__ void load_k(const PassArgs& a, int j, long long g0, long long d, float2 (&v)[K],
+                                       float& asum) {
+  if constexpr (LM == LM_REAL) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) v[r] = make_float2(a.src_r[g0 + r * d], 0.f);
+  } else if constexpr (LM == LM_C) {
+    const float2* p = a.src_c + j * a.src_stride;
+#pragma unroll
+    for (int r = 0; r < K; ++r) v[r] = p[g0 + r * d];
+  } else if constexpr (LM == LM_MULBANK) {
+    const float* pr = a.psi + (long long)a.rows[j] * a.V;
+    float ps[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) ps[r] = pr[g0 + r * d];
+#pragma unroll
+    for (int r = 0; r < K; ++r) v[r] = a.src_c[g0 + r * d];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      v[r] = cscale(v[r], ps[r]);
+      asum += sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
+    }
+  } else if constexpr (LM == LM_UIN) {
+    const int ia = a.oa[j], ib = a.ob[j];
+    float sa = 1.f, sb = 1.f;
+    if constexpr (DT != OS3D_C64) {
+      sa = a.scales[ia];
+      if (ib >= 0) sb = a.scales[ib];
+    }
+    const long long ba = (long long)ia * a.V + g0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) v[r] = load_score<DT>(a.U, ba + r * d, sa);
+    if (ib >= 0) {
+      const long long bb = (long long)ib * a.V + g0;
+      float2 w[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) w[r] = load_score<DT>(a.U, bb + r * d, sb);
+#pragma unroll
+      for (int r = 0; r < K; ++r) v[r] = cadd(v[r], cconj(w[r]));
+    }
+  } else {  // LM_DIVM
+#pragma unroll
+    for (int r = 0; r < K; ++r) v[r] = a.src_c[g0 + r * d];
+    if (a.divide) {
+      float m[K];
+#pragma unroll
+      for (int r = 0; r < K; ++r) m[r] = a.M[g0 + r * d];
+#pragma unroll
+      for (int r = 0; r < K; ++r) v[r] = cscale(v[r], 1.f / fmaxf(m[r], a.eps));
+    }
+  }
+}
+
+// K values of one thread stored at g0 + r d for pair slot j; SM_ACCUM adds
+// psi_hat_j * value into acc[r] instead.
+template <int SM, int DT, int K>
+__device__ __forceinline__ void store_k(const PassArgs& a, int j, long long g0, long long d, const float2 (&v)[K],
+                                        float2 (&acc)[K]) {
+  if constexpr (SM == SM_C) {
+    float2* p = a.dst_c + j * a.dst_stride;
+#pragma unroll
+    for (int r = 0; r < K; ++r) p[g0 + r * d] = v[r];
+  } else if constexpr (SM == SM_UOUT) {
+    const int ia = a.oa[j], ib = a.ob[j];
+    const float inv_s = (DT != OS3D_C64) ? 1.f / a.scales[ia] : 1.f;
+    const long long ba = (long long)ia * a.V + g0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) store_score<DT>(a.Uout, ba + r * d, cscale(v[r], a.out_scale), inv_s);
+    if (ib >= 0) {
+      const long long bb = (long long)ib * a.V + g0;
+#pragma unroll
+      for (int r = 0; r < K; ++r) store_score<DT>(a.Uout, bb + r * d, cconj(cscale(v[r], a.out_scale)), inv_s);
+    }
+  } else if constexpr (SM == SM_ACCUM) {
+    const float* pr = a.psi + (long long)a.rows[j] * a.V;
+    float ps[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) ps[r] = pr[g0 + r * d];
+#pragma unroll
+    for (int r = 0; r < K; ++r) acc[r] = make_float2(acc[r].x + ps[r] * v[r].x, acc[r].y + ps[r] * v[r].y);
+  } else {  // SM_REAL
+#pragma unroll
+    for (int r = 0; r < K; ++r) a.dst_r[g0 + r * d] = v[r].x * a.out_scale;
+  }
+}
+
+// X (+)= acc at g0 + r d, the read of X (when adding) issued as one group.
+template <int K>
+__device__ __forceinline__ void flush_k(const PassArgs& a, long long g0, long long d, const float2 (&acc)[K]) {
+  if (a.accumulate) {
+    float2 x[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) x[r] = a.dst_c[g0 + r * d];
+#pragma unroll
+    for (int r = 0; r < K; ++r) a.dst_c[g0 + r * d] = cadd(x[r], acc[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < K; ++r) a.dst_c[g0 + r * d] = acc[r];
+  }
+}
+
 // Per-kernel timer slots (os3d_profile_*): first / middle / last pass of the
 // DFT of f, of the forward transform, of the reconstruction's orientation
 // sum and of its final inverse DFT.

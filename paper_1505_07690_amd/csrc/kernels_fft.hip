@@ -239,9 +239,14 @@ __global__ __launch_bounds__(kThreads) void k_fast(PassArgs a) {
   for (int j = jb; j < je; ++j) {
     float2 v[16];
     float asum = 0.f;
+    if (valid) {
+      const long long g0 = gaddr_t<N, AXIS>(a, line, s);
+      const long long dn = gaddr_t<N, AXIS>(a, line, s + C::TL) - g0;
+      load_k<LM, DT, 16>(a, j, g0, dn, v, asum);
+    } else {
 #pragma unroll
-    for (int r = 0; r < 16; ++r)
-      v[r] = valid ? load_elem<LM, DT>(a, j, gaddr_t<N, AXIS>(a, line, s + C::TL * r), asum) : make_float2(0.f, 0.f);
+      for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
+    }
     if constexpr (LM == LM_MULBANK) {
       if (a.partial) {
         red[t] = asum;
@@ -267,8 +272,14 @@ __global__ __launch_bounds__(kThreads) void k_fast(PassArgs a) {
       for (int r = 1; r < C::R2; ++r) u[r] = cmul(u[r], twl[jj * r]);
       dft_r<C::R2>(u, a.sgn);
       if (valid) {
+        const long long g0 = gaddr_t<N, AXIS>(a, line, jj);
+        const long long dn = gaddr_t<N, AXIS>(a, line, jj + 16) - g0;
+        float2 ac[C::R2];
 #pragma unroll
-        for (int r = 0; r < C::R2; ++r) store_elem<SM, DT>(a, j, gaddr_t<N, AXIS>(a, line, jj + 16 * r), u[r], acc[q * C::R2 + r]);
+        for (int r = 0; r < C::R2; ++r) ac[r] = acc[q * C::R2 + r];
+        store_k<SM, DT, C::R2>(a, j, g0, dn, u, ac);
+#pragma unroll
+        for (int r = 0; r < C::R2; ++r) acc[q * C::R2 + r] = ac[r];
       }
     }
     __syncthreads();
@@ -276,9 +287,14 @@ __global__ __launch_bounds__(kThreads) void k_fast(PassArgs a) {
   if constexpr (SM == SM_ACCUM) {
     if (valid) {
 #pragma unroll
-      for (int q = 0; q < C::B2; ++q)
+      for (int q = 0; q < C::B2; ++q) {
+        const long long g0 = gaddr_t<N, AXIS>(a, line, s + C::TL * q);
+        const long long dn = gaddr_t<N, AXIS>(a, line, s + C::TL * q + 16) - g0;
+        float2 ac[C::R2];
 #pragma unroll
-        for (int r = 0; r < C::R2; ++r) accum_flush(a, gaddr_t<N, AXIS>(a, line, s + C::TL * q + 16 * r), acc[q * C::R2 + r]);
+        for (int r = 0; r < C::R2; ++r) ac[r] = acc[q * C::R2 + r];
+        flush_k<C::R2>(a, g0, dn, ac);
+      }
     }
   }
 }

@@ -74,9 +74,7 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
   float2 spec[16];
   {
     float unused = 0.f;
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-      spec[r] = load_elem<(LM == LM_MULBANK) ? LM_C : LM>(a, 0, base + r * 1024 + t, unused);
+    load_k<(LM == LM_MULBANK) ? LM_C : LM, OS3D_C64, 16>(a, 0, base + t, 1024, spec, unused);
   }
   float pnx[16];
   if constexpr (LM == LM_MULBANK) {
@@ -170,9 +168,8 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
   for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
   dft16(v, a.sgn);
   const long long row = ((long long)(4 * zb + g) * 256 + (16 * k1 + k2)) * 256;
-  float2 dummy;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) store_elem<SM, DT>(a, j, row + s + 16 * r, v[r], dummy);
+  float2 dummy[16];
+  store_k<SM, DT, 16>(a, j, row + s, 16, v, dummy);
 }
 
 // Natural side of the forward direction: rows y = n1 + 16 n2 of four z
@@ -191,8 +188,7 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
   const long long row = ((long long)(4 * zb + g) * 256 + (n1 + 16 * n2)) * 256;
   float2 v[16];
   float asum = 0.f;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = load_elem<LM, DT>(a, j, row + s + 16 * r, asum);
+  load_k<LM, DT, 16>(a, j, row + s, 16, v, asum);
   dft16(v, a.sgn);
   float2* S = lds + g * k4Sub + n2 * k4LS;
 #pragma unroll
@@ -262,14 +258,10 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
     for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
     dft16(v, a.sgn);
     // kz = s + 16 r sits at Phi position pbase + r * 1024 + t
-#pragma unroll
-    for (int r = 0; r < 16; ++r) store_elem<SM>(a, j, pbase + r * 1024 + t, v[r], acc[r]);
+    store_k<SM, OS3D_C64, 16>(a, j, pbase + t, 1024, v, acc);
     if constexpr (SM == SM_ACCUM) __syncthreads();
   }
-  if constexpr (SM == SM_ACCUM) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) accum_flush(a, pbase + r * 1024 + t, acc[r]);
-  }
+  if constexpr (SM == SM_ACCUM) flush_k<16>(a, pbase + t, 1024, acc);
 }
 
 static int check(const char* what) {
