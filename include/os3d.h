@@ -58,6 +58,11 @@ typedef enum {
   OS3D_PLATE = 1     /* h = A: real plate detector (Sec. 3.1, Fig. 4) */
 } os3d_variant;
 
+typedef enum {
+  OS3D_PHI_IDENTITY = 0,        /* Phi(U) = U: Upsilon = W^+ W, the band filter M / max(M, eps) */
+  OS3D_PHI_SOFT_THRESHOLD = 1   /* Phi(U) = |U|^p sgn(U), sgn(U) = U / |U| (Fig. 7: p = 1.5) */
+} os3d_phi;
+
 /* Cake-wavelet parameters (Sec. 3).
  *   L         spherical-harmonic order of the window expansion (Eq. 15), 0 <= L <= 64
  *   s_theta   width of the orientation window A = B^k(theta / s_theta) (Eq. 11), > 0
@@ -88,7 +93,7 @@ typedef struct {
   int32_t n_unique;      /* stored bank rows: N_o/2 when the set is antipodally closed, else N_o */
   int32_t paired;        /* 1 when every orientation has its antipode in the set */
   double kappa;          /* normaliser: the band mean of M is 1 */
-  double M_min_band;     /* (reserved, 0) */
+  double approx_norm;    /* S: band mean of sum_i psi_hat_i, normaliser of os3d_reconstruct_approx */
   const float* M_dev;    /* M[k] on the device, frequency order of os3d_bank_M */
 } os3d_bank_info;
 
@@ -156,6 +161,25 @@ os3d_status os3d_adjoint(const os3d_bank* bank, const void* U, int32_t dtype, co
  * f_out[b] = Re IDFT(sum_i psi_hat_i DFT(U[b][i]) / max(M, eps)). */
 os3d_status os3d_reconstruct(const os3d_bank* bank, const void* U, int32_t dtype, const float* scales,
                              int32_t batch, float* f_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Approximate reconstruction, Eq. (6): the integral of the score over the
+ * orientations, f_out[b] = Re(sum_i U[b][i]) / S, where S normalises the
+ * discrete area element so that sum_i psi_hat_i averages 1 over the band
+ * (|omega| <= rho_N / 2, the band of kappa).  No DFT: one pass over the scores
+ * (Sec. 3.1 names it as the alternative to the stabilised inverse).
+ * Arguments as for os3d_reconstruct; no workspace. */
+os3d_status os3d_reconstruct_approx(const os3d_bank* bank, const void* U, int32_t dtype, const float* scales,
+                                    int32_t batch, float* f_out, void* stream);
+
+/* Processing via invertible orientation scores, Eq. (23) with the
+ * stabilised inverse: f_out[b] = Re W^+ (Phi(W f[b])) for a pointwise
+ * operation Phi on the scores (os3d_phi; phi_power is p of the soft
+ * threshold, 0 < p <= 16).  Both kinds satisfy Phi(conj U) = conj Phi(U), so
+ * for real f an antipodal pair contributes 2 Phi(U_n) to the orientation sum
+ * and the scores never reach memory.  f, f_out: float32 [B][Nz][Ny][Nx];
+ * ws: os3d_workspace_bytes bytes. */
+os3d_status os3d_process(const os3d_bank* bank, const float* f, int32_t batch, int32_t phi, double phi_power,
+                         float* f_out, void* ws, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing (not a method step: measurement support).  While
  * enabled, every launch of the transform's kernels is bracketed by two HIP

@@ -43,7 +43,8 @@ __all__ = [
     "geodesic_icosahedron", "sh_coeffs_A", "sh_coeffs_A_quadrature",
     "cake_coeffs", "angular_profile", "freq_grid", "steering_matrix",
     "build_bank", "bank_values", "band_kappa", "forward", "adjoint", "reconstruct",
-    "forward_bruteforce", "spatial_wavelets", "quantize_scores", "fit_zonal",
+    "forward_bruteforce", "spatial_wavelets", "quantize_scores", "fit_zonal", "approx_norm",
+    "reconstruct_approx", "soft_threshold", "process",
 ]
 
 
@@ -413,6 +414,43 @@ def reconstruct(U, bank, eps=None):
     eps = bank["params"].eps if eps is None else eps
     X = _orientation_sum(np.asarray(U), bank)
     return np.real(idft3(X / np.maximum(bank["M"], eps)))
+
+
+def approx_norm(bank):
+    """S = mean over the band of sum_i psi_hat_i[k]: the discrete area element
+    of Eq. (6) normalised so that the orientation sum of the bank averages 1."""
+    wz, wy, wx, nyq = freq_grid(bank["shape"])
+    rho = np.sqrt(wx * wx + wy * wy + wz * wz)
+    band = (rho > 0) & (rho <= RHO_N / 2) & ~nyq
+    return float(np.mean(np.sum(bank["psi_hat"], axis=0)[band]))
+
+
+def reconstruct_approx(U, bank):
+    """Approximate reconstruction of Eq. (6): the integral of the score over
+    the orientations, Re(sum_i U_i) / S (no inverse filter)."""
+    return np.real(np.sum(np.asarray(U), axis=0)) / approx_norm(bank)
+
+
+def soft_threshold(U, p):
+    """Phi(U) = |U|^p sgn(U), sgn(U) = U / |U| (0 where U = 0): the pointwise
+    score operation of Fig. 7 (p = 1.5 there), applied to the complex score."""
+    U = np.asarray(U)
+    m = np.abs(U)
+    out = np.zeros_like(U)
+    nz = m > 0
+    out[nz] = U[nz] * m[nz] ** (p - 1.0)
+    return out
+
+
+def process(f, bank, phi="soft_threshold", p=1.5):
+    """Processing via invertible orientation scores, Eq. (23): the stabilised
+    reconstruction of Phi applied to the score of f."""
+    U = forward(f, bank)
+    if phi == "soft_threshold":
+        U = soft_threshold(U, p)
+    elif phi != "identity":
+        raise ValueError(phi)
+    return reconstruct(U, bank)
 
 
 def forward_bruteforce(f, bank):

@@ -14,7 +14,7 @@ namespace os3d {
 constexpr int kMaxBatch = 16;    // orientation pairs per launch
 
 enum LoadMode { LM_REAL = 0, LM_C = 1, LM_MULBANK = 2, LM_UIN = 3, LM_DIVM = 4 };
-enum StoreMode { SM_C = 0, SM_UOUT = 1, SM_ACCUM = 2, SM_REAL = 3 };
+enum StoreMode { SM_C = 0, SM_UOUT = 1, SM_ACCUM = 2, SM_REAL = 3, SM_PHI = 4 };
 
 struct PassArgs {
   int axis;  // 0 = z, 1 = y, 2 = x
@@ -48,6 +48,8 @@ struct PassArgs {
   float out_scale;
   float* partial;        // [nb][tiles] sums of |value| (scale bound), or null
   int accumulate;        // SM_ACCUM: 1 adds to X, 0 overwrites
+  int phi_kind;          // SM_PHI: 0 identity, 1 |U|^phi_p sgn(U)
+  float phi_p;
 };
 
 __device__ __forceinline__ long long gaddr(const PassArgs& a, long long line, int n) {
@@ -147,6 +149,15 @@ __device__ __forceinline__ void store_elem(const PassArgs& a, int j, long long g
   } else if constexpr (SM == SM_ACCUM) {
     const float p = a.psi[(long long)a.rows[j] * a.V + g];
     acc = make_float2(acc.x + p * v.x, acc.y + p * v.y);
+  } else if constexpr (SM == SM_PHI) {
+    const float2 u = cscale(v, a.out_scale);
+    const float mult = (a.ob[j] >= 0) ? 2.f : 1.f;
+    float f = mult;
+    if (a.phi_kind == 1) {
+      const float m = sqrtf(u.x * u.x + u.y * u.y);
+      f = (m > 0.f) ? mult * powf(m, a.phi_p - 1.f) : 0.f;
+    }
+    a.dst_c[j * a.dst_stride + g] = cscale(u, f);
   } else {  // SM_REAL
     a.dst_r[g] = v.x * a.out_scale;
   }
@@ -243,6 +254,23 @@ __device__ __forceinline__ void store_k(const PassArgs& a, int j, long long g0, 
     for (int r = 0; r < K; ++r) ps[r] = pr[g0 + r * d];
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] = make_float2(acc[r].x + ps[r] * v[r].x, acc[r].y + ps[r] * v[r].y);
+  } else if constexpr (SM == SM_PHI) {
+    // the pointwise map of the score, stored as the reconstruction's input
+    // for the pair: Phi(U_n) + conj(Phi(U_-n)) = 2 Phi(U_n) for real f
+    float2* p = a.dst_c + j * a.dst_stride;
+    const float mult = (a.ob[j] >= 0) ? 2.f : 1.f;
+    if (a.phi_kind == 1) {
+#pragma unroll
+      for (int r = 0; r < K; ++r) {
+        const float2 u = cscale(v[r], a.out_scale);
+        const float m = sqrtf(u.x * u.x + u.y * u.y);
+        const float f = (m > 0.f) ? mult * powf(m, a.phi_p - 1.f) : 0.f;
+        p[g0 + r * d] = cscale(u, f);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < K; ++r) p[g0 + r * d] = cscale(v[r], mult * a.out_scale);
+    }
   } else {  // SM_REAL
 #pragma unroll
     for (int r = 0; r < K; ++r) a.dst_r[g0 + r * d] = v[r].x * a.out_scale;
@@ -278,5 +306,7 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
              void* stream);
 int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out, void* ws,
             bool divide_M, int nbmax, void* stream);
+int process4(const os3d_bank* b, const float* f, int batch, int phi_kind, float phi_p, float* f_out, void* ws,
+             int nbmax, void* stream);
 
 }  // namespace os3d

@@ -12,6 +12,7 @@
 // epilogue multiplies by the FP64 radial window g(rho) (Eq. 10), applies the
 // Nyquist and DC rules, writes the bank rows and accumulates
 // sum_i psi_i^2 (Eq. 9) in FP64 with a fixed-order cross-lane tree.
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -258,6 +259,86 @@ __global__ void k_kappa_final(double* part, int nparts) {
   }
 }
 
+// Partial sums over the band of sum_i psi_hat_i[k] (all orientations: a
+// stored row counts at k and, for an antipodal pair, at -k): the normaliser
+// of the approximate reconstruction of Eq. (6).
+__global__ __launch_bounds__(256) void k_approx_partial(const float* psi, int n_rows, int paired, int layout, int Nz,
+                                                        int Ny, int Nx, long long V, double* part) {
+  __shared__ double ssum[256];
+  __shared__ double scnt[256];
+  const int tid = threadIdx.x;
+  const long long chunk = (V + gridDim.x - 1) / gridDim.x;
+  const long long b = (long long)blockIdx.x * chunk, e = min(V, b + chunk);
+  double s = 0.0, cnt = 0.0;
+  const double half = 0.5 * 3.14159265358979323846;
+  for (long long p = b + tid; p < e; p += 256) {
+    int kz, ky, kx;
+    pos_to_k(layout, p, Nz, Ny, Nx, kz, ky, kx);
+    if (is_nyquist(kx, Nx) || is_nyquist(ky, Ny) || is_nyquist(kz, Nz)) continue;
+    double wx = omega_of(kx, Nx), wy = omega_of(ky, Ny), wz = omega_of(kz, Nz);
+    double rho = sqrt(wx * wx + wy * wy + wz * wz);
+    if (rho > 0.0 && rho <= half) {
+      const long long q = paired ? mirror_index(layout, p, Nz, Ny, Nx) : p;
+      double t = 0.0;
+      for (int r = 0; r < n_rows; ++r) {
+        t += (double)psi[(long long)r * V + p];
+        if (paired) t += (double)psi[(long long)r * V + q];
+      }
+      s += t;
+      cnt += 1.0;
+    }
+  }
+  ssum[tid] = s;
+  scnt[tid] = cnt;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      ssum[tid] += ssum[tid + w];
+      scnt[tid] += scnt[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[2 * blockIdx.x] = ssum[0];
+    part[2 * blockIdx.x + 1] = scnt[0];
+  }
+}
+
+__global__ void k_approx_final(double* part, int nparts) {
+  if (threadIdx.x == 0) {
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < nparts; ++i) {
+      s += part[2 * i];
+      c += part[2 * i + 1];
+    }
+    part[2 * nparts + 1] = (c > 0.0) ? s / c : 1.0;
+  }
+}
+
+// f_out[b] = Re(sum_i U[b][i]) / S: the orientation integral of Eq. (6), one
+// pass over the scores, fixed summation order (deterministic).
+template <int DT>
+__global__ __launch_bounds__(256) void k_approx_reconstruct(const void* U, const float* scales, int n_orients,
+                                                            long long V, float inv_norm, float* out) {
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= V) return;
+  float acc = 0.f;
+  for (int i = 0; i < n_orients; ++i) {
+    if constexpr (DT == OS3D_C64) {
+      acc += ((const float2*)U)[(long long)i * V + p].x;
+    } else {
+      const unsigned int q = ((const unsigned int*)U)[(long long)i * V + p];
+      float re;
+      if constexpr (DT == OS3D_F16X2)
+        re = __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
+      else
+        re = __uint_as_float((q & 0xffffu) << 16);
+      acc += re * scales[i];
+    }
+  }
+  out[p] = acc * inv_norm;
+}
+
 // psi *= kappa; M = kappa^2 M0.
 __global__ __launch_bounds__(256) void k_bank_finalize(float* psi, int n_rows, double* Mh, float* M, int paired,
                                                        int layout, int Nz, int Ny, int Nx, long long V,
@@ -348,13 +429,44 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   hipLaunchKernelGGL(k_bank_finalize, dim3(fin_blocks), dim3(256), 0, st, b->d.psi, b->n_unique, b->d.Mh, b->d.M,
                      b->paired, b->layout, a.Nz, a.Ny, a.Nx, a.V, b->d.part + 2 * nparts);
   if ((rc = check_launch("k_bank_finalize"))) return rc;
-  double kappa = 0.0;
-  if (hipMemcpyAsync(&kappa, b->d.part + 2 * nparts, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  hipLaunchKernelGGL(k_approx_partial, dim3(nparts), dim3(256), 0, st, b->d.psi, b->n_unique, b->paired, b->layout,
+                     a.Nz, a.Ny, a.Nx, a.V, b->d.part);
+  if ((rc = check_launch("k_approx_partial"))) return rc;
+  hipLaunchKernelGGL(k_approx_final, dim3(1), dim3(64), 0, st, b->d.part, nparts);
+  if ((rc = check_launch("k_approx_final"))) return rc;
+  double kn[2] = {0.0, 0.0};
+  if (hipMemcpyAsync(kn, b->d.part + 2 * nparts, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
     set_error("os3d_build_bank: reading kappa failed");
     return OS3D_EDEVICE;
   }
-  b->kappa = kappa;
+  b->kappa = kn[0];
+  b->approx_norm = kn[1];
+  return OS3D_OK;
+}
+
+int launch_approx(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out,
+                  void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const size_t ubytes = (dtype == OS3D_C64) ? 8 : 4;
+  const unsigned nblk = (unsigned)((b->V + 255) / 256);
+  const float inv_norm = (float)(1.0 / b->approx_norm);
+  for (int bi = 0; bi < batch; ++bi) {
+    const void* Ub = (const char*)U + (size_t)bi * b->n_orients * b->V * ubytes;
+    const float* sc = scales ? scales + (long long)bi * b->n_orients : nullptr;
+    float* o = f_out + (long long)bi * b->V;
+    if (dtype == OS3D_C64)
+      hipLaunchKernelGGL(k_approx_reconstruct<OS3D_C64>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients, b->V,
+                         inv_norm, o);
+    else if (dtype == OS3D_BF16X2)
+      hipLaunchKernelGGL(k_approx_reconstruct<OS3D_BF16X2>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients,
+                         b->V, inv_norm, o);
+    else
+      hipLaunchKernelGGL(k_approx_reconstruct<OS3D_F16X2>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients,
+                         b->V, inv_norm, o);
+    int rc = check_launch("k_approx_reconstruct");
+    if (rc) return rc;
+  }
   return OS3D_OK;
 }
 

@@ -483,7 +483,9 @@ size_t workspace_bytes(const os3d_bank* b) {
     const int W = std::min(256, std::max(1, kTile / n));
     max_tiles = std::max(max_tiles, (long long)((b->V / n + W - 1) / W));  // fast kernels use W = 4096 / n too
   }
-  return (size_t)(1 + nb) * b->V * sizeof(float2) + (size_t)nb * max_tiles * sizeof(float) + 256;
+  // F or X, one intermediate per pair of the batch; processing via scores (F, X, and two
+  // buffers per pair of a half batch) needs one volume more
+  return (size_t)(2 + std::max(nb, 2)) * b->V * sizeof(float2) + (size_t)nb * max_tiles * sizeof(float) + 256;
 }
 
 // forward DFT of one real volume into F (three passes, in place after the first)
@@ -640,6 +642,103 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
     z.M = b->d.M;
     z.eps = (float)b->params.eps;
     z.divide = divide_M ? 1 : 0;
+    z.dst_c = X;
+    if ((rc = run_pass<LM_DIVM, SM_C>(kProfInvFirst, 0.0, z, 1, st))) return rc;
+    PassArgs y = {};
+    setup_axis(b, 1, y);
+    y.sgn = 1.f;
+    y.nb = 1;
+    y.src_c = X;
+    y.dst_c = X;
+    if ((rc = run_pass<LM_C, SM_C>(kProfInvMid, 0.0, y, 1, st))) return rc;
+    PassArgs x = {};
+    setup_axis(b, 2, x);
+    x.sgn = 1.f;
+    x.nb = 1;
+    x.src_c = X;
+    x.dst_r = f_out + (long long)bi * V;
+    x.out_scale = 1.f / (float)V;
+    if ((rc = run_pass<LM_C, SM_REAL>(kProfInvLast, 4.0 * b->V, x, 1, st))) return rc;
+  }
+  return OS3D_OK;
+}
+
+// Processing via scores, Eq. (23) with the stabilised inverse, on the
+// three-pass path (see process4 for the structure).
+int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, float phi_p, float* f_out, void* ws,
+                   void* stream) {
+  const int nbp = std::max(1, pair_batch(b) / 2);
+  if (b->layout == kLayoutFour256) return process4(b, f, batch, phi_kind, phi_p, f_out, ws, nbp, stream);
+  hipStream_t st = (hipStream_t)stream;
+  const long long V = b->V;
+  float2* F = (float2*)ws;
+  float2* X = F + V;
+  float2* T = X + V;
+  float2* Z = T + (long long)nbp * V;
+  int rc;
+  for (int bi = 0; bi < batch; ++bi) {
+    if ((rc = dft_real_volume(b, f + (long long)bi * V, F, st))) return rc;
+    for (int r0 = 0; r0 < b->n_unique; r0 += nbp) {
+      const int nb = std::min(nbp, b->n_unique - r0);
+      PassArgs z = {};
+      setup_axis(b, 0, z);
+      z.sgn = 1.f;
+      z.nb = nb;
+      for (int j = 0; j < nb; ++j) {
+        const int o = b->rep[r0 + j];
+        z.rows[j] = r0 + j;
+        z.oa[j] = o;
+        z.ob[j] = b->partner[o];
+      }
+      z.src_c = F;
+      z.psi = b->d.psi;
+      z.dst_c = T;
+      z.dst_stride = V;
+      if ((rc = run_pass<LM_MULBANK, SM_C>(kProfFwdFirst, 0.0, z, nb, st))) return rc;
+      PassArgs y = z;
+      setup_axis(b, 1, y);
+      y.src_c = T;
+      y.src_stride = V;
+      if ((rc = run_pass<LM_C, SM_C>(kProfFwdMid, 0.0, y, nb, st))) return rc;
+      PassArgs x = z;
+      setup_axis(b, 2, x);
+      x.src_c = T;
+      x.src_stride = V;
+      x.dst_c = Z;
+      x.dst_stride = V;
+      x.out_scale = 1.f / (float)V;
+      x.phi_kind = phi_kind;
+      x.phi_p = phi_p;
+      if ((rc = run_pass<LM_C, SM_PHI>(kProfFwdLast, 0.0, x, nb, st))) return rc;
+      PassArgs u = z;
+      setup_axis(b, 2, u);
+      u.sgn = -1.f;
+      u.src_c = Z;
+      u.src_stride = V;
+      u.dst_c = T;
+      u.dst_stride = V;
+      if ((rc = run_pass<LM_C, SM_C>(kProfRecFirst, 0.0, u, nb, st))) return rc;
+      PassArgs v = u;
+      setup_axis(b, 1, v);
+      v.src_c = T;
+      if ((rc = run_pass<LM_C, SM_C>(kProfRecMid, 0.0, v, nb, st))) return rc;
+      PassArgs w = u;
+      setup_axis(b, 0, w);
+      w.src_c = T;
+      w.psi = b->d.psi;
+      w.dst_c = X;
+      w.dst_stride = 0;
+      w.accumulate = (r0 > 0) ? 1 : 0;
+      if ((rc = run_pass<LM_C, SM_ACCUM>(kProfRecLast, 0.0, w, 1, st))) return rc;
+    }
+    PassArgs z = {};
+    setup_axis(b, 0, z);
+    z.sgn = 1.f;
+    z.nb = 1;
+    z.src_c = X;
+    z.M = b->d.M;
+    z.eps = (float)b->params.eps;
+    z.divide = 1;
     z.dst_c = X;
     if ((rc = run_pass<LM_DIVM, SM_C>(kProfInvFirst, 0.0, z, 1, st))) return rc;
     PassArgs y = {};

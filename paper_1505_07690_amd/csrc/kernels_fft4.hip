@@ -431,4 +431,95 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
   return OS3D_OK;
 }
 
+// Processing via scores, Eq. (23) with the stabilised inverse: per pair
+// batch the forward transform's last pass applies Phi and writes the
+// reconstruction's input 2 Phi(U_n) (the score itself never reaches memory),
+// then the two forward-direction passes accumulate the orientation sum.
+int process4(const os3d_bank* b, const float* f, int batch, int phi_kind, float phi_p, float* f_out, void* ws,
+             int nbmax, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const long long V = b->V;
+  float2* F = (float2*)ws;
+  float2* X = F + V;
+  float2* T = X + V;
+  float2* Z = T + (long long)nbmax * V;
+  int rc;
+  for (int bi = 0; bi < batch; ++bi) {
+    {
+      PassArgs a = base_args(b, -1.f);
+      a.src_r = f + (long long)bi * V;
+      a.dst_c = T;
+      OS3D_LAUNCH4((k4_fwd_nat<LM_REAL, OS3D_C64>), kProfDftFirst, 4.0 * V, a, 1);
+      PassArgs c = base_args(b, -1.f);
+      c.src_c = T;
+      c.dst_c = F;
+      OS3D_LAUNCH4((k4_fwd_phi<SM_C>), kProfDftLast, 0.0, c, 1);
+    }
+    for (int r0 = 0; r0 < b->n_unique; r0 += nbmax) {
+      const int nb = std::min(nbmax, b->n_unique - r0);
+      PassArgs z = base_args(b, 1.f);
+      z.nb = nb;
+      for (int jj = 0; jj < nb; ++jj) {
+        const int o = b->rep[r0 + jj];
+        z.rows[jj] = r0 + jj;
+        z.oa[jj] = o;
+        z.ob[jj] = b->partner[o];
+      }
+      z.src_c = F;
+      z.psi = b->d.psi;
+      z.dst_c = T;
+      z.dst_stride = V;
+      OS3D_LAUNCH4((k4_inv_phi<LM_MULBANK>), kProfFwdFirst, 0.0, z, 1);
+      PassArgs x = z;
+      x.src_c = T;
+      x.src_stride = V;
+      x.dst_c = Z;
+      x.dst_stride = V;
+      x.out_scale = 1.f / (float)V;
+      x.phi_kind = phi_kind;
+      x.phi_p = phi_p;
+      {
+        void* tok = prof_start(st);
+        hipLaunchKernelGGL((k4_inv_nat<SM_PHI, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        prof_stop(tok, st, kProfFwdLast, 0.0, 0.0);
+        if ((rc = check("k4_inv_nat"))) return rc;
+      }
+      PassArgs y = base_args(b, -1.f);
+      y.nb = nb;
+      for (int jj = 0; jj < nb; ++jj) y.rows[jj] = z.rows[jj];
+      y.src_c = Z;
+      y.src_stride = V;
+      y.dst_c = T;
+      y.dst_stride = V;
+      {
+        void* tok = prof_start(st);
+        hipLaunchKernelGGL((k4_fwd_nat<LM_C, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, y);
+        prof_stop(tok, st, kProfRecFirst, 0.0, 0.0);
+        if ((rc = check("k4_fwd_nat"))) return rc;
+      }
+      PassArgs w = y;
+      w.src_c = T;
+      w.src_stride = V;
+      w.psi = b->d.psi;
+      w.dst_c = X;
+      w.dst_stride = 0;
+      w.accumulate = (r0 > 0) ? 1 : 0;
+      OS3D_LAUNCH4((k4_fwd_phi<SM_ACCUM>), kProfRecLast, 0.0, w, 1);
+    }
+    PassArgs z = base_args(b, 1.f);
+    z.src_c = X;
+    z.M = b->d.M;
+    z.eps = (float)b->params.eps;
+    z.divide = 1;
+    z.dst_c = T;
+    OS3D_LAUNCH4((k4_inv_phi<LM_DIVM>), kProfInvFirst, 0.0, z, 1);
+    PassArgs x = base_args(b, 1.f);
+    x.src_c = T;
+    x.dst_r = f_out + (long long)bi * V;
+    x.out_scale = 1.f / (float)V;
+    OS3D_LAUNCH4((k4_inv_nat<SM_REAL, OS3D_C64>), kProfInvLast, 4.0 * V, x, 1);
+  }
+  return OS3D_OK;
+}
+
 }  // namespace os3d

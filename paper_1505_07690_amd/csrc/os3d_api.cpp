@@ -273,7 +273,7 @@ os3d_status os3d_get_bank_info(const os3d_bank* b, os3d_bank_info* info) {
   info->n_unique = b->n_unique;
   info->paired = b->paired;
   info->kappa = b->kappa;
-  info->M_min_band = 0.0;
+  info->approx_norm = b->approx_norm;
   info->M_dev = b->d.M;
   return OS3D_OK;
 }
@@ -329,6 +329,27 @@ os3d_status os3d_reconstruct(const os3d_bank* b, const void* U, int32_t dtype, c
   int rc = check_compute(b, U, batch, f_out, dtype, scales, ws, ws_bytes, false);
   if (rc) return (os3d_status)rc;
   return (os3d_status)launch_reduce(b, U, dtype, scales, batch, f_out, ws, true, stream);
+}
+
+os3d_status os3d_reconstruct_approx(const os3d_bank* b, const void* U, int32_t dtype, const float* scales,
+                                    int32_t batch, float* f_out, void* stream) {
+  if (!b) return (os3d_status)fail(OS3D_EINVAL, "bank is NULL");
+  if (!U || !f_out) return (os3d_status)fail(OS3D_EINVAL, "input or output is NULL");
+  if (batch < 1) return (os3d_status)fail(OS3D_EINVAL, "batch must be >= 1");
+  if (dtype != OS3D_C64 && dtype != OS3D_BF16X2 && dtype != OS3D_F16X2)
+    return (os3d_status)fail(OS3D_EINVAL, "unknown score dtype");
+  if (dtype != OS3D_C64 && !scales) return (os3d_status)fail(OS3D_EINVAL, "scales is NULL for a 16-bit score dtype");
+  return (os3d_status)launch_approx(b, U, dtype, scales, batch, f_out, stream);
+}
+
+os3d_status os3d_process(const os3d_bank* b, const float* f, int32_t batch, int32_t phi, double phi_power,
+                         float* f_out, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_compute(b, f, batch, f_out, OS3D_C64, nullptr, ws, ws_bytes, false);
+  if (rc) return (os3d_status)rc;
+  if (phi != OS3D_PHI_IDENTITY && phi != OS3D_PHI_SOFT_THRESHOLD) return (os3d_status)fail(OS3D_EINVAL, "unknown phi");
+  if (phi == OS3D_PHI_SOFT_THRESHOLD && !(phi_power > 0.0 && phi_power <= 16.0))
+    return (os3d_status)fail(OS3D_EINVAL, "phi_power must be in (0, 16]");
+  return (os3d_status)launch_process(b, f, batch, phi, (float)phi_power, f_out, ws, stream);
 }
 
 os3d_status os3d_profile_enable(int32_t on) { return (os3d_status)profile_enable(on); }

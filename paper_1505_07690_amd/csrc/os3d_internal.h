@@ -88,6 +88,7 @@ struct os3d_bank {
   int K;
   double kappa;
   double dc_value;            // a_0 / sqrt(4 pi): the sphere average of h, used at k = 0
+  double approx_norm;         // band mean of sum_i psi_hat_i (approximate reconstruction)
   os3d_wavelet_params params;
   std::vector<int> partner;   // per orientation: antipode index or -1
   std::vector<int> row_of;    // per orientation: stored bank row
@@ -107,6 +108,10 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
 int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out,
                   void* ws, bool divide_M, void* stream);
 int launch_export_psi(const os3d_bank* b, int i, float* out, void* stream);
+int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, float phi_p, float* f_out, void* ws,
+                   void* stream);
+int launch_approx(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out,
+                  void* stream);
 int launch_export_M(const os3d_bank* b, float* out, void* stream);
 size_t workspace_bytes(const os3d_bank* b);
 int profile_enable(int on);

@@ -33,7 +33,7 @@ class Params(ctypes.Structure):
 
 class BankInfo(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int64 * 3), ("n_orients", ctypes.c_int32), ("n_unique", ctypes.c_int32),
-                ("paired", ctypes.c_int32), ("kappa", ctypes.c_double), ("M_min_band", ctypes.c_double),
+                ("paired", ctypes.c_int32), ("kappa", ctypes.c_double), ("approx_norm", ctypes.c_double),
                 ("M_dev", ctypes.c_void_p)]
 
 
@@ -57,6 +57,10 @@ _SIGS = {
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "os3d_reconstruct": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "os3d_reconstruct_approx": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                ctypes.c_void_p, ctypes.c_void_p],
+    "os3d_process": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "os3d_profile_enable": [ctypes.c_int32],
     "os3d_profile_count": [ctypes.POINTER(ctypes.c_int32)],
     "os3d_profile_get": [ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64),
@@ -162,6 +166,7 @@ class Bank:
         info = BankInfo()
         _check(lib().os3d_get_bank_info(self.handle, ctypes.byref(info)))
         self.kappa = info.kappa
+        self.approx_norm = info.approx_norm
         self.n_unique = info.n_unique
         self.paired = bool(info.paired)
         n = ctypes.c_size_t()
@@ -265,6 +270,45 @@ def adjoint(U, bank, scales=None, dtype="c64", ws=None, out=None, stream=None):
 def reconstruct(U, bank, scales=None, dtype="c64", ws=None, out=None, stream=None):
     """Stabilised exact reconstruction, Eq. (8) with max(M, eps)."""
     return _reduce(lib().os3d_reconstruct, U, bank, scales, dtype, ws, out, stream)
+
+
+def reconstruct_approx(U, bank, scales=None, dtype="c64", out=None, stream=None):
+    """Approximate reconstruction of Eq. (6): Re(sum_i U_i) / S."""
+    import torch
+    code = DTYPES[dtype]
+    Ub = U if U.dim() == 5 else U.unsqueeze(0)
+    if not Ub.is_contiguous():
+        raise ValueError("U must be contiguous")
+    B = Ub.shape[0]
+    if out is None:
+        out = torch.empty((B,) + bank.shape, dtype=torch.float32, device=Ub.device)
+    sc = None
+    if code != OS3D_C64:
+        sc = scales if scales.dim() == 2 else scales.unsqueeze(0)
+    _check(lib().os3d_reconstruct_approx(bank.handle, ctypes.c_void_p(Ub.data_ptr()), code,
+                                         ctypes.c_void_p(sc.data_ptr() if sc is not None else 0), B,
+                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out if U.dim() == 5 else out[0]
+
+
+PHIS = {"identity": 0, "soft_threshold": 1}
+
+
+def process(f, bank, phi="soft_threshold", power=1.5, ws=None, out=None, stream=None):
+    """Processing via scores, Eq. (23): Re W^+ Phi(W f) with a pointwise Phi
+    ("identity" or "soft_threshold": |U|^power sgn(U))."""
+    import torch
+    fb, single = _batched(f, bank.shape)
+    if fb.dtype != torch.float32 or not fb.is_contiguous():
+        raise ValueError("f must be a contiguous float32 tensor")
+    B = fb.shape[0]
+    if out is None:
+        out = torch.empty((B,) + bank.shape, dtype=torch.float32, device=fb.device)
+    ws = bank.workspace() if ws is None else ws
+    _check(lib().os3d_process(bank.handle, ctypes.c_void_p(fb.data_ptr()), B, PHIS[phi], float(power),
+                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                              _stream_ptr(stream)))
+    return out[0] if single else out
 
 
 def unpack16(Uq, scales, dtype):

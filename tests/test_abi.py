@@ -28,7 +28,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol():
     L = os3d.lib()
     syms = declared_symbols()
-    assert len(syms) == 17, syms
+    assert len(syms) == 19, syms
     for s in syms:
         assert hasattr(L, s), s
     assert L.os3d_version().decode().startswith("os3d")
@@ -102,6 +102,8 @@ def test_errors_are_status_codes():
     assert L.os3d_forward(None, None, 1, None, 0, None, None, 0, None) == -1
     assert L.os3d_reconstruct(None, None, 0, None, 1, None, None, 0, None) == -1
     assert L.os3d_adjoint(None, None, 0, None, 1, None, None, 0, None) == -1
+    assert L.os3d_reconstruct_approx(None, None, 0, None, 1, None, None) == -1
+    assert L.os3d_process(None, None, 1, 0, 1.5, None, None, 0, None) == -1
     assert L.os3d_free_bank(None) == 0
 
 

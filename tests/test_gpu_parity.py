@@ -203,3 +203,31 @@ def test_reduced_precision_storage(torch_dev, fmt, bound):
     j = np.argmin(d, axis=1)
     Uc = os3d.unpack16(Uq, sc, fmt)
     assert torch_dev.equal(Uc[j], torch_dev.conj(Uc).resolve_conj())
+
+
+def test_approximate_reconstruction_parity(case):
+    """Eq. (6) on the GPU (one pass over the scores) against the oracle, for
+    a general complex score and for 16-bit storage."""
+    from paper_1505_07690_amd import os3d
+    import torch
+    rng = np.random.default_rng(2)
+    No = len(case["orients"])
+    Un = (rng.standard_normal((No,) + case["shape"]) + 1j * rng.standard_normal((No,) + case["shape"]))
+    Un32 = Un.astype(np.complex64)
+    got = os3d.reconstruct_approx(torch.from_numpy(Un32).cuda(), case["gb"]).cpu().numpy()
+    assert abs(case["gb"].approx_norm - O.approx_norm(case["ob"])) < 1e-6 * abs(O.approx_norm(case["ob"]))
+    assert rel(got, O.reconstruct_approx(Un32.astype(np.complex128), case["ob"])) < TOL
+    Uq, sc = os3d.forward(case["f"], case["gb"], dtype="fp16")
+    got16 = os3d.reconstruct_approx(Uq, case["gb"], scales=sc, dtype="fp16").cpu().numpy()
+    want = O.reconstruct_approx(O.forward(case["vol"].astype(np.float64), case["ob"]), case["ob"])
+    assert rel(got16, want) < 5e-4
+
+
+@pytest.mark.parametrize("phi,power", [("identity", 1.0), ("soft_threshold", 1.5)])
+def test_process_parity(case, phi, power):
+    """Eq. (23), W^+ Phi(W f), fused on the GPU (Phi applied in the forward
+    transform's last pass) against the oracle."""
+    from paper_1505_07690_amd import os3d
+    got = os3d.process(case["f"], case["gb"], phi, power).cpu().numpy()
+    want = O.process(case["vol"].astype(np.float64), case["ob"], phi, power)
+    assert rel(got, want) < TOL

@@ -487,3 +487,89 @@ def test_quantisation_roundtrip_bounds():
     # bf16 rounding is to nearest, ties to even
     x = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -9], dtype=np.float32)
     assert list(O.os3d_oracle._bf16_round(x)) == [1.0, 1 + 2 ** -6, 1.0]
+
+
+# ------------------------------------------- approximate reconstruction ----
+
+def test_approx_reconstruction_is_the_orientation_sum_multiplier():
+    """Eq. (6): Re sum_i U_i / S equals the single Fourier multiplier
+    (sum_i psi_hat_i / S) applied to f (per-orientation inverse DFTs vs one)."""
+    b, n, p = _setup((10, 8, 12), level=1, L=16)
+    f = np.random.default_rng(21).standard_normal((10, 8, 12))
+    lhs = O.reconstruct_approx(O.forward(f, b), b)
+    rhs = np.real(O.idft3(np.sum(b["psi_hat"], axis=0) / O.approx_norm(b) * O.dft3(f)))
+    assert rel(lhs, rhs) < 1e-13
+
+
+def test_approx_reconstruction_L0_is_normalised_lowpass():
+    """L = 0: every psi_hat_i is kappa g a_0 / sqrt(4 pi), so Eq. (6) is the
+    radial window divided by its band mean."""
+    shape = (12, 12, 12)
+    b, n, p = _setup(shape, level=0, L=0)
+    f = np.random.default_rng(22).standard_normal(shape)
+    wz, wy, wx, nyq = O.freq_grid(shape)
+    rho = np.sqrt(wx ** 2 + wy ** 2 + wz ** 2)
+    g = np.where(nyq, 0.0, O.radial_g(rho, p.gamma, p.taylor_N))
+    band = (rho > 0) & (rho <= np.pi / 2) & ~nyq
+    want = np.real(O.idft3(g / g[band].mean() * O.dft3(f)))
+    assert rel(O.reconstruct_approx(O.forward(f, b), b), want) < 1e-13
+
+
+def test_approx_reconstruction_accuracy_bandlimited():
+    """Eq. (6) holds approximately: for volumes band-limited to half the
+    Nyquist radius (where the radial window is ~1) the 42-orientation cake
+    wavelets reproduce f to better than 1 %; nearer Nyquist it blurs."""
+    shape = (24, 24, 24)
+    b, n, p = _setup(shape, level=1, L=16)
+    f = inputs.bandlimited(shape, 0.5, seed=1, dtype=np.float64)
+    assert rel(O.reconstruct_approx(O.forward(f, b), b), f) < 1e-2
+    f2 = inputs.bandlimited(shape, 0.9, seed=1, dtype=np.float64)
+    assert rel(O.reconstruct_approx(O.forward(f2, b), b), f2) > 2e-2
+
+
+def test_orientation_sum_of_bank_is_even_for_antipodal_sets():
+    """For an antipodal set the odd (edge-detecting) parts cancel in
+    sum_i psi_hat_i, so the approximate reconstruction of real data is real."""
+    b, n, p = _setup((8, 10, 6), level=1, L=16)
+    Ssum = np.sum(b["psi_hat"], axis=0)
+    mirrored = np.roll(np.flip(Ssum, axis=(0, 1, 2)), 1, axis=(0, 1, 2))
+    assert np.max(np.abs(Ssum - mirrored)) < 1e-13 * np.max(np.abs(Ssum))
+
+
+# ------------------------------------------- processing via scores ----
+
+def test_soft_threshold_values():
+    """Fig. 7's Phi(U) = |U|^p sgn(U): real scores keep their sign; for a
+    complex score sgn(U) = U / |U| keeps the phase (3+4i has modulus 5)."""
+    got = O.soft_threshold(np.array([-4.0, 0.0, 9.0]), 1.5)
+    assert np.allclose(got, [-8.0, 0.0, 27.0], rtol=0, atol=1e-12)
+    z = O.soft_threshold(np.array([3 + 4j, -2j]), 1.5)
+    assert abs(z[0] - (3 + 4j) * np.sqrt(5.0)) < 1e-12
+    assert abs(z[1] - (-2j) * np.sqrt(2.0)) < 1e-12
+
+
+def test_process_identity_is_the_gram_filter():
+    """Eq. (23) with Phi = id is W^+ W: the single multiplier M / max(M, eps)
+    on DFT(f) (one transform pair instead of N_o of them); with p = 1 the
+    soft threshold is the identity."""
+    shape = (10, 8, 12)
+    b, n, p = _setup(shape, level=1, L=16)
+    f = np.random.default_rng(23).standard_normal(shape)
+    want = np.real(O.idft3(O.dft3(f) * b["M"] / np.maximum(b["M"], p.eps)))
+    assert rel(O.process(f, b, "identity"), want) < 1e-13
+    assert rel(O.process(f, b, "soft_threshold", 1.0), want) < 1e-13
+
+
+def test_process_soft_threshold_homogeneity_and_oddness():
+    """|c U|^p sgn(c U) = c^p Phi(U) for c > 0 and Phi(-U) = -Phi(U), and W,
+    W^+ are linear: the processed volume is p-homogeneous and odd in f."""
+    shape = (8, 10, 6)
+    b, n, p = _setup(shape, level=0, L=8)
+    f = np.random.default_rng(24).standard_normal(shape)
+    g = O.process(f, b, "soft_threshold", 1.5)
+    assert rel(O.process(3.0 * f, b, "soft_threshold", 1.5), 3.0 ** 1.5 * g) < 1e-12
+    assert rel(O.process(-f, b, "soft_threshold", 1.5), -g) < 1e-12
+    # a nonlinear Phi: not a multiple of the identity result
+    lin = O.process(f, b, "identity")
+    c = np.sum(g * lin) / np.sum(lin * lin)
+    assert rel(g, c * lin) > 1e-2
