@@ -32,6 +32,8 @@ WORKLOADS = {
     # name: (config key of the volume recipe, human label)
     "C": "256^3 crossing tubes (40 tubes, sigma U[1,4], noise 0.3, seed 2), N_o=162, L=24",
     "B": "128^3 crossing tubes (12 tubes, 5 forced crossings, noise 0.2, seed 1), N_o=42, L=16",
+    "E": "serving: Poisson stream of forward+reconstruct jobs (50 req/s, seed 4), shapes 64^3, 96x80x64, 128^3, "
+         "160x128x128, 256^3, N_o in {42, 162}, L in {16, 24}, 12 crossing tubes per volume",
 }
 
 
@@ -44,6 +46,12 @@ def parse():
     ap.add_argument("--dtype", default="c64", choices=["c64", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-orients", type=int, default=4, help="orientations in the oracle's timed sample")
+    ap.add_argument("--requests", type=int, default=1000, help="serving: requests in the stream")
+    ap.add_argument("--rate", type=float, default=50.0, help="serving: mean arrivals per second")
+    ap.add_argument("--hbm-budget-gb", type=float, default=160.0, help="serving: HBM budget of the server")
+    ap.add_argument("--slots", type=int, default=4, help="serving: concurrent launches (streams)")
+    ap.add_argument("--max-batch", type=int, default=8, help="serving: jobs per batched launch")
+    ap.add_argument("--cold", action="store_true", help="serving: start with an empty bank cache")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     return ap.parse_args()
@@ -128,6 +136,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.workload == "E":
+        serve_main(args, dev)
+        return
 
     if args.copy_calibration:
         n = 1 << 28  # 1 GiB of float32
@@ -235,6 +247,110 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_orients)
+    print(json.dumps(out), flush=True)
+
+
+def serve_main(args, dev):
+    """Serving workload: the Poisson stream through the continuous-batching
+    server (latency), the same requests submitted at once (served capacity),
+    and the same requests run one after another without the server (plain),
+    with served and plain results compared on a sample."""
+    import numpy as np
+    import torch
+
+    from paper_1505_07690_amd import inputs, os3d, serve
+
+    reqs = inputs.serving_stream(args.requests, args.rate, seed=4)
+    pool_n = 4  # distinct volumes per shape; a request takes pool[seed % pool_n]
+    pool = {sh: [inputs.tubes_device(sh, 12, (1.0, 3.0), 0.2, 0, 1000 + 17 * i + k, device=dev)
+                 for k in range(pool_n)] for i, sh in enumerate(inputs.SERVING_SHAPES)}
+    torch.cuda.synchronize()
+    vol_of = [pool[sh][seed % pool_n] for (_, sh, _, _, seed) in reqs]
+    vo = [int(np.prod(sh)) * n for (_, sh, n, _, _) in reqs]
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    ex = serve.GpuExecutor(n_slots=args.slots)
+    print(f"[bench] serving {len(reqs)} requests at {args.rate}/s, budget {args.hbm_budget_gb} GB, "
+          f"{args.slots} slots", file=sys.stderr, flush=True)
+
+    def run_server(times):
+        srv = serve.Server(budget, n_slots=args.slots, max_batch=args.max_batch, executor=ex)
+        if not args.cold:  # banks of every key, built before the stream
+            for key in sorted({(sh, n, L) for (_, sh, n, L, _) in reqs}):
+                srv.submit(pool[key[0]][0], key[1], key[2]).result()
+            srv.records.clear()
+            srv.bank_hits = srv.bank_misses = 0
+        keep = {}
+        t0 = time.perf_counter()
+        for i, (_, sh, n, L, seed) in enumerate(reqs):
+            if times is not None:
+                dt = t0 + times[i] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            fut = srv.submit(vol_of[i], n, L)
+            if i % max(1, len(reqs) // 16) == 0:
+                keep[i] = fut
+        srv.close()
+        return srv, keep
+
+    srv, _ = run_server([r[0] for r in reqs])
+    stream = srv.stats()
+    print(f"[bench] stream: p50 {stream.get('p50_ms', 0):.2f} ms p99 {stream.get('p99_ms', 0):.2f} ms",
+          file=sys.stderr, flush=True)
+    srv2, kept = run_server(None)
+    sat = srv2.stats()
+
+    # plain: the same jobs one after another on one stream, banks cached
+    banks = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (_, sh, n, L, seed) in enumerate(reqs):
+        key = (sh, n, L)
+        if key not in banks:
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            banks[key] = os3d.Bank(sh, serve._orients(n), serve._params(n, L))
+            torch.cuda.synchronize()
+            t0 += time.perf_counter() - tb  # bank builds are not job time
+        b = banks[key]
+        U, _ = os3d.forward(vol_of[i], b)
+        r = os3d.reconstruct(U, b)
+        del U, r
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    worst, equal = 0.0, True
+    for i, fut in kept.items():
+        _, sh, n, L, _ = reqs[i]
+        b = banks[(sh, n, L)]
+        U, _ = os3d.forward(vol_of[i], b)
+        ref = os3d.reconstruct(U, b)
+        got = fut.result()
+        worst = max(worst, (torch.linalg.norm(got - ref) / torch.linalg.norm(ref)).item())
+        equal &= bool(torch.equal(got, ref))
+    out = {
+        "metric": "voxel-orientations/sec forward+reconstruct, %HBM roofline; p50/p99 latency",
+        "value": sat["vo_per_s"],
+        "unit": "voxel-orientations/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 0,
+        "ms_per_step": sat["span_s"] * 1e3 / len(reqs),
+        "p50_ms": stream["p50_ms"],
+        "p99_ms": stream["p99_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["E"], "requests": len(reqs), "rate_per_s": args.rate,
+                   "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "max_batch": args.max_batch,
+                   "warm_bank_cache": not args.cold, "volume_pool_per_shape": pool_n},
+        "stream": stream,
+        "saturation": sat,
+        "plain_sequential": {"vo_per_s": sum(vo) / plain_s, "span_s": plain_s},
+        "served_vs_plain": {"sampled": len(kept), "max_rel_l2": worst, "bit_equal": equal},
+        "peak_torch_allocated_gb": torch.cuda.max_memory_allocated() / 2 ** 30,
+        "roofline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

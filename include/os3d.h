@@ -59,6 +59,13 @@ typedef enum {
 } os3d_variant;
 
 typedef enum {
+  OS3D_COEFFS_LSQ = 0,        /* c_l by least squares (the pseudo-inverse) over the frequency-15 geodesic
+                                 icosahedron, as in Sec. 3.2 */
+  OS3D_COEFFS_QUADRATURE = 1  /* c_l = 2 pi int_0^pi A(theta) Y_l0(theta) sin(theta) dtheta, composite
+                                 64-node Gauss-Legendre in theta split at the B-spline knots */
+} os3d_coeffs;
+
+typedef enum {
   OS3D_PHI_IDENTITY = 0,        /* Phi(U) = U: Upsilon = W^+ W, the band filter M / max(M, eps) */
   OS3D_PHI_SOFT_THRESHOLD = 1   /* Phi(U) = |U|^p sgn(U), sgn(U) = U / |U| (Fig. 7: p = 1.5) */
 } os3d_phi;
@@ -71,7 +78,8 @@ typedef enum {
  *   gamma     inflection point of the radial window at gamma * rho_N (Sec. 3.1), 0 < gamma < 1
  *   eps       floor in M -> max(M, eps) of the stabilised inverse (Sec. 3.1), > 0
  *             (M vanishes on the Nyquist planes of even dims)
- *   variant   os3d_variant */
+ *   variant   os3d_variant
+ *   coeffs    os3d_coeffs: how the SH coefficients of A are obtained */
 typedef struct {
   int32_t L;
   double s_theta;
@@ -80,6 +88,7 @@ typedef struct {
   double gamma;
   double eps;
   int32_t variant;
+  int32_t coeffs;
 } os3d_wavelet_params;
 
 /* Opaque host handle of a built bank: dims, orientation pairing, kappa and
@@ -98,8 +107,9 @@ typedef struct {
 } os3d_bank_info;
 
 /* Host-only wavelet design (Sec. 3.1-3.2), FP64, no device needed.
- * c_out[0..L]: coefficients c_{l,0} of A fitted by least squares (the
- * pseudo-inverse) over the frequency-15 geodesic icosahedron (Eq. 15);
+ * c_out[0..L]: coefficients c_{l,0} of A (Eq. 15) by the method p->coeffs
+ * selects (least squares over the frequency-15 geodesic icosahedron, or the
+ * quadrature projection);
  * a_out[0..L]: coefficients of h (cake: 2 pi P_l(0) c_l + (1 - (-1)^l) c_l,
  * Eqs. 12-16; plate: c_l).  Either output may be NULL. */
 os3d_status os3d_wavelet_coeffs(const os3d_wavelet_params* p, double* c_out, double* a_out);

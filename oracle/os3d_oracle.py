@@ -53,7 +53,7 @@ class WaveletParams:
     s_theta and B-spline order k (Eq. 11), Taylor order N_T and inflection
     fraction gamma of the radial window (Eq. 10), stabiliser eps (Sec. 3.1)."""
 
-    def __init__(self, L=16, s_theta=0.7, k=2, taylor_N=20, gamma=0.8, eps=1e-3, variant="cake"):
+    def __init__(self, L=16, s_theta=0.7, k=2, taylor_N=20, gamma=0.8, eps=1e-3, variant="cake", coeffs="lsq"):
         self.L = int(L)
         self.s_theta = float(s_theta)
         self.k = int(k)
@@ -61,10 +61,12 @@ class WaveletParams:
         self.gamma = float(gamma)
         self.eps = float(eps)
         self.variant = variant  # "cake" (Eq. 14) or "plate" (h = A, Fig. 4)
+        self.coeffs = coeffs    # "lsq" (pseudo-inverse fit, Sec. 3.2) or "quadrature" (projection)
 
     def __repr__(self):
         return (f"WaveletParams(L={self.L}, s_theta={self.s_theta}, k={self.k}, "
-                f"taylor_N={self.taylor_N}, gamma={self.gamma}, eps={self.eps}, variant={self.variant!r})")
+                f"taylor_N={self.taylor_N}, gamma={self.gamma}, eps={self.eps}, variant={self.variant!r}, "
+                f"coeffs={self.coeffs!r})")
 
 
 # ---------------------------------------------------------------------------
@@ -260,9 +262,9 @@ def sh_coeffs_A(params, freq=15):
 
 def sh_coeffs_A_quadrature(params, nodes=64):
     """Projection c_l = 2 pi int_0^pi A(theta) Y_l^0(theta) sin(theta) dtheta
-    by composite Gauss-Legendre in theta split at the B-spline knots (a
-    cross-check of the least-squares fit; they differ by the fit's
-    discretisation error only)."""
+    by composite Gauss-Legendre in theta split at the B-spline knots: the
+    alternative to the least-squares fit (params.coeffs = "quadrature"),
+    differing from it by the fit's discretisation error only."""
     L, k, s = params.L, params.k, params.s_theta
     knots = [0.0] + [s * (j - (k + 1) / 2.0) for j in range(k + 2)
                      if 0.0 < s * (j - (k + 1) / 2.0) < math.pi] + [math.pi]
@@ -369,7 +371,7 @@ def build_bank(shape, orients, params):
     psi_hat_i^2 (Eq. 9 with its constants absorbed into kappa), kappa, and
     the coefficient vectors (c, a)."""
     shape = tuple(int(s) for s in shape)
-    c = sh_coeffs_A(params)
+    c = sh_coeffs_A_quadrature(params) if params.coeffs == "quadrature" else sh_coeffs_A(params)
     a = cake_coeffs(c, params.variant)
     wz, wy, wx, nyq = freq_grid(shape)
     raw = bank_values(wz, wy, wx, nyq, orients, a, params)

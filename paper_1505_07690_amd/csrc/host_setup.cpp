@@ -147,15 +147,76 @@ void cake_coeffs(int L, const double* c, int variant, double* a) {
   }
 }
 
-void wavelet_coeffs(const os3d_wavelet_params& p, std::vector<double>& c, std::vector<double>& a) {
-  std::vector<double> pts = geodesic_icosahedron(15);
-  const int np = (int)pts.size() / 3;
-  std::vector<double> vals(np);
-  for (int i = 0; i < np; ++i) {
-    double z = std::max(-1.0, std::min(1.0, pts[3 * i + 2]));
-    vals[i] = bspline(p.k, std::acos(z) / p.s_theta);
+// Gauss-Legendre nodes (ascending) and weights on [-1, 1]: Newton's method on
+// P_n from the asymptotic initial guesses.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = -std::cos(kPi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int j = 2; j <= n; ++j) {
+      const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
   }
-  zonal_fit(p.L, pts, vals, c);
+}
+
+// c_l = 2 pi int_0^pi A(theta) Y_l0(theta) sin(theta) dtheta, 64 Gauss-Legendre
+// nodes on each interval between the knots of B^k(theta / s_theta).
+static void quadrature_coeffs(const os3d_wavelet_params& p, std::vector<double>& c) {
+  std::vector<double> knots = {0.0, kPi};
+  for (int j = 0; j <= p.k + 1; ++j) {
+    const double t = p.s_theta * (j - (p.k + 1) / 2.0);
+    if (t > 0.0 && t < kPi) knots.push_back(t);
+  }
+  std::sort(knots.begin(), knots.end());
+  knots.erase(std::unique(knots.begin(), knots.end()), knots.end());
+  std::vector<double> xg, wg, P(p.L + 1);
+  gauss_legendre(64, xg, wg);
+  c.assign(p.L + 1, 0.0);
+  for (size_t q = 0; q + 1 < knots.size(); ++q) {
+    const double a = knots[q], b = knots[q + 1];
+    for (int i = 0; i < 64; ++i) {
+      const double th = 0.5 * (b - a) * xg[i] + 0.5 * (b + a);
+      const double wt = 0.5 * (b - a) * wg[i];
+      legendre(p.L, std::cos(th), P.data());
+      const double f = bspline(p.k, th / p.s_theta) * std::sin(th) * wt;
+      for (int l = 0; l <= p.L; ++l) c[l] += 2.0 * kPi * std::sqrt((2.0 * l + 1.0) / (4.0 * kPi)) * P[l] * f;
+    }
+  }
+}
+
+void wavelet_coeffs(const os3d_wavelet_params& p, std::vector<double>& c, std::vector<double>& a) {
+  if (p.coeffs == OS3D_COEFFS_QUADRATURE) {
+    quadrature_coeffs(p, c);
+  } else {
+    std::vector<double> pts = geodesic_icosahedron(15);
+    const int np = (int)pts.size() / 3;
+    std::vector<double> vals(np);
+    for (int i = 0; i < np; ++i) {
+      double z = std::max(-1.0, std::min(1.0, pts[3 * i + 2]));
+      vals[i] = bspline(p.k, std::acos(z) / p.s_theta);
+    }
+    zonal_fit(p.L, pts, vals, c);
+  }
   a.assign(p.L + 1, 0.0);
   cake_coeffs(p.L, c.data(), p.variant, a.data());
 }

@@ -472,7 +472,10 @@ static double score_bytes(const os3d_bank* b, const PassArgs& a, int nb, size_t 
 static int pair_batch(const os3d_bank* b) {
   int nb = kMaxBatch;
   if (const char* e = getenv("OS3D_PAIR_BATCH")) nb = atoi(e);
-  return std::max(1, std::min(std::min(nb, kMaxBatch), b->n_unique));
+  nb = std::max(1, std::min(std::min(nb, kMaxBatch), b->n_unique));
+  // the same number of pairs in every launch (no short last launch)
+  const int launches = (b->n_unique + nb - 1) / nb;
+  return (b->n_unique + launches - 1) / launches;
 }
 
 size_t workspace_bytes(const os3d_bank* b) {

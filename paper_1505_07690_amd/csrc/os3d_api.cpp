@@ -34,6 +34,8 @@ static int check_params(const os3d_wavelet_params* p) {
   if (!(p->gamma > 0.0 && p->gamma < 1.0)) return fail(OS3D_EINVAL, "gamma must be in (0, 1)");
   if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(OS3D_EINVAL, "eps must be > 0");
   if (p->variant != OS3D_CAKE && p->variant != OS3D_PLATE) return fail(OS3D_EINVAL, "unknown variant");
+  if (p->coeffs != OS3D_COEFFS_LSQ && p->coeffs != OS3D_COEFFS_QUADRATURE)
+    return fail(OS3D_EINVAL, "unknown coefficient method");
   return OS3D_OK;
 }
 

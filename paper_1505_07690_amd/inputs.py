@@ -18,7 +18,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["tubes", "icosahedral_orientations", "bandlimited", "CONFIGS", "config_volume"]
+__all__ = ["tubes", "tubes_device", "icosahedral_orientations", "bandlimited", "CONFIGS", "config_volume",
+           "serving_stream", "SERVING_SHAPES"]
 
 
 def _unit(v):
@@ -26,22 +27,8 @@ def _unit(v):
     return v / np.linalg.norm(v)
 
 
-def tubes(shape, n_tubes, sigma, noise, n_cross_pairs=0, seed=0):
-    """Sum of straight tubes with Gaussian cross-section plus white noise.
-
-    shape: (Nz, Ny, Nx); voxel centres sit at integer coordinates; the
-    returned array is float32 [Nz][Ny][Nx] (x fastest).
-    sigma: a float (every tube) or a (lo, hi) range drawn uniformly per tube.
-    The first ``2 * n_cross_pairs`` tubes come in forced crossing pairs whose
-    axes pass within 4 voxels of each other.
-
-    Draw order (PCG64 via numpy.random.default_rng(seed)): for every tube in
-    turn, pairs first: [pair: q (3), u_a (3), u_b (3), delta (1)] or
-    [single: u (3), c (3)]; then all sigmas (n_tubes, if a range); then the
-    noise field.
-    """
+def _tube_params(shape, n_tubes, sigma, n_cross_pairs, rng):
     nz, ny, nx = (int(s) for s in shape)
-    rng = np.random.default_rng(seed)
     ext = np.array([nx, ny, nz], dtype=np.float64)
     dirs, cents = [], []
     t = 0
@@ -62,6 +49,26 @@ def tubes(shape, n_tubes, sigma, noise, n_cross_pairs=0, seed=0):
         sig = np.full(n_tubes, float(sigma))
     else:
         sig = rng.uniform(sigma[0], sigma[1], n_tubes)
+    return dirs, cents, sig
+
+
+def tubes(shape, n_tubes, sigma, noise, n_cross_pairs=0, seed=0):
+    """Sum of straight tubes with Gaussian cross-section plus white noise.
+
+    shape: (Nz, Ny, Nx); voxel centres sit at integer coordinates; the
+    returned array is float32 [Nz][Ny][Nx] (x fastest).
+    sigma: a float (every tube) or a (lo, hi) range drawn uniformly per tube.
+    The first ``2 * n_cross_pairs`` tubes come in forced crossing pairs whose
+    axes pass within 4 voxels of each other.
+
+    Draw order (PCG64 via numpy.random.default_rng(seed)): for every tube in
+    turn, pairs first: [pair: q (3), u_a (3), u_b (3), delta (1)] or
+    [single: u (3), c (3)]; then all sigmas (n_tubes, if a range); then the
+    noise field.
+    """
+    nz, ny, nx = (int(s) for s in shape)
+    rng = np.random.default_rng(seed)
+    dirs, cents, sig = _tube_params(shape, n_tubes, sigma, n_cross_pairs, rng)
     z = np.arange(nz, dtype=np.float64)[:, None, None]
     y = np.arange(ny, dtype=np.float64)[None, :, None]
     x = np.arange(nx, dtype=np.float64)[None, None, :]
@@ -73,6 +80,47 @@ def tubes(shape, n_tubes, sigma, noise, n_cross_pairs=0, seed=0):
         f += np.exp(-np.maximum(d2, 0.0) / (2.0 * s * s))
     f += noise * rng.standard_normal((nz, ny, nx))
     return f.astype(np.float32)
+
+
+def tubes_device(shape, n_tubes, sigma, noise, n_cross_pairs=0, seed=0, device="cuda"):
+    """The same tube geometry as ``tubes`` (same parameter draws), evaluated
+    in float32 with torch on `device`; the noise comes from a torch generator
+    seeded with `seed`, so the values differ from ``tubes`` by the noise
+    field and float32 rounding.  For request streams whose volumes are made
+    on the device."""
+    import torch
+    nz, ny, nx = (int(s) for s in shape)
+    rng = np.random.default_rng(seed)
+    dirs, cents, sig = _tube_params(shape, n_tubes, sigma, n_cross_pairs, rng)
+    z = torch.arange(nz, dtype=torch.float32, device=device)[:, None, None]
+    y = torch.arange(ny, dtype=torch.float32, device=device)[None, :, None]
+    x = torch.arange(nx, dtype=torch.float32, device=device)[None, None, :]
+    f = torch.zeros((nz, ny, nx), dtype=torch.float32, device=device)
+    for u, c, s in zip(dirs, cents, sig):
+        dx, dy, dz = x - float(c[0]), y - float(c[1]), z - float(c[2])
+        along = dx * float(u[0]) + dy * float(u[1]) + dz * float(u[2])
+        d2 = (dx * dx + dy * dy + dz * dz - along * along).clamp_min_(0.0)
+        f += torch.exp(d2 * (-0.5 / float(s * s)))
+    g = torch.Generator(device=device).manual_seed(int(seed))
+    f += noise * torch.randn((nz, ny, nx), generator=g, device=device, dtype=torch.float32)
+    return f
+
+
+def serving_stream(n_requests=1000, rate=50.0, seed=4):
+    """Poisson request stream: exponential gaps of mean 1/rate seconds; per
+    request a shape from SERVING_SHAPES, N_o from {42, 162} and L from
+    {16, 24} drawn independently and uniformly, and a volume seed.  Returns
+    a list of (t_arrival_s, shape, n_orients, L, volume_seed)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for _ in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        shape = SERVING_SHAPES[int(rng.integers(len(SERVING_SHAPES)))]
+        n = (42, 162)[int(rng.integers(2))]
+        L = (16, 24)[int(rng.integers(2))]
+        out.append((t, shape, n, L, int(rng.integers(2 ** 31))))
+    return out
 
 
 def _icosahedron():
@@ -164,6 +212,10 @@ CONFIGS = {
     "B": dict(shape=(128, 128, 128), tubes=12, sigma=(1.0, 3.0), noise=0.2, pairs=5, seed=1, level=1, L=16),
     "C": dict(shape=(256, 256, 256), tubes=40, sigma=(1.0, 4.0), noise=0.3, pairs=0, seed=2, level=2, L=24),
 }
+
+
+# Request shapes (z, y, x) of the serving workload.
+SERVING_SHAPES = [(64, 64, 64), (96, 80, 64), (128, 128, 128), (160, 128, 128), (256, 256, 256)]
 
 
 def config_volume(name):

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libos3d.so")
 OS3D_C64, OS3D_BF16X2, OS3D_F16X2 = 0, 1, 2
 DTYPES = {"c64": OS3D_C64, "bf16": OS3D_BF16X2, "fp16": OS3D_F16X2}
 VARIANTS = {"cake": 0, "plate": 1}
+COEFFS = {"lsq": 0, "quadrature": 1}
 
 
 class OS3DError(RuntimeError):
@@ -28,7 +29,7 @@ class OS3DError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("s_theta", ctypes.c_double), ("k", ctypes.c_int32),
                 ("taylor_N", ctypes.c_int32), ("gamma", ctypes.c_double), ("eps", ctypes.c_double),
-                ("variant", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("coeffs", ctypes.c_int32)]
 
 
 class BankInfo(ctypes.Structure):
@@ -93,9 +94,10 @@ def _check(rc):
         raise OS3DError(rc, lib().os3d_last_error().decode())
 
 
-def make_params(L=16, s_theta=0.7, k=2, taylor_N=20, gamma=0.8, eps=1e-3, variant="cake"):
+def make_params(L=16, s_theta=0.7, k=2, taylor_N=20, gamma=0.8, eps=1e-3, variant="cake", coeffs="lsq"):
     return Params(int(L), float(s_theta), int(k), int(taylor_N), float(gamma), float(eps),
-                  VARIANTS[variant] if isinstance(variant, str) else int(variant))
+                  VARIANTS[variant] if isinstance(variant, str) else int(variant),
+                  COEFFS[coeffs] if isinstance(coeffs, str) else int(coeffs))
 
 
 def _as_params(p):
@@ -104,7 +106,8 @@ def _as_params(p):
     if isinstance(p, dict):
         return make_params(**p)
     # any object with the attributes (e.g. the oracle's WaveletParams)
-    return make_params(p.L, p.s_theta, p.k, p.taylor_N, p.gamma, p.eps, getattr(p, "variant", "cake"))
+    return make_params(p.L, p.s_theta, p.k, p.taylor_N, p.gamma, p.eps, getattr(p, "variant", "cake"),
+                       getattr(p, "coeffs", "lsq"))
 
 
 def _orients(o):

@@ -46,6 +46,17 @@ def test_host_coefficients_match_oracle(L, s, variant):
     assert np.max(np.abs(a_lib - a_or)) < 1e-12 * max(1.0, np.max(np.abs(a_or)))
 
 
+@pytest.mark.parametrize("L,s,k", [(8, 1.31, 2), (24, 0.356, 2), (16, 0.5, 3), (6, 1.0, 0)])
+def test_host_quadrature_coefficients_match_oracle(L, s, k):
+    """The quadrature projection option: composite Gauss-Legendre at the
+    B-spline knots, host C++ against the oracle."""
+    p = O.WaveletParams(L=L, s_theta=s, k=k, coeffs="quadrature")
+    c_lib, a_lib = os3d.wavelet_coeffs(p)
+    c_or = O.sh_coeffs_A_quadrature(p)
+    assert np.max(np.abs(c_lib - c_or)) < 1e-13 * max(1.0, np.max(np.abs(c_or)))
+    assert np.max(np.abs(a_lib - O.cake_coeffs(c_or))) < 1e-12 * max(1.0, np.max(np.abs(c_or)))
+
+
 def test_host_steering_matrix_blocks():
     """Eqs. 17-19 by the addition theorem: for every l,
     sum_m S[lm, i] S[lm, j] = a_l^2 (4 pi / (2l+1)) (2l+1)/(4 pi) P_l(n_i . n_j),

@@ -63,6 +63,10 @@ CASES = {
     # 256 on z, 128 on y, tiny x: a y-tile wraps across z planes
     "fast256x128x4": lambda: ((256, 128, 4), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                               inputs.tubes((256, 128, 4), 2, 1.0, 0.1, 0, 11)),
+    # quadrature coefficients, B-spline order 3 and a narrow window (bank variants)
+    "quad_k3": lambda: ((12, 16, 10), inputs.icosahedral_orientations(1),
+                        O.WaveletParams(L=12, s_theta=0.5, k=3, coeffs="quadrature"),
+                        inputs.tubes((12, 16, 10), 2, 1.2, 0.1, 0, 12)),
     # small N with radix-2 only and a long axis
     "long4x6x64": lambda: ((4, 6, 64), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                            inputs.tubes((4, 6, 64), 2, 1.0, 0.1, 0, 8)),

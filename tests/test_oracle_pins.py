@@ -573,3 +573,34 @@ def test_process_soft_threshold_homogeneity_and_oddness():
     lin = O.process(f, b, "identity")
     c = np.sum(g * lin) / np.sum(lin * lin)
     assert rel(g, c * lin) > 1e-2
+
+
+# ------------------------------------------- coefficient method ----
+
+@pytest.mark.parametrize("s", [0.4, 0.9, 1.7])
+def test_quadrature_coeffs_closed_forms(s):
+    """The projection c_l = 2 pi int A Y_l0 sin(theta) dtheta in closed form:
+    k = 0 (box of half-width s/2; with c = cos(s/2): c_0 = sqrt(pi)(1 - c),
+    c_1 = sqrt(3 pi) sin^2(s/2) / 2, c_2 = sqrt(5 pi)(c - c^3) / 2) and
+    k = 1 (triangle of half-width s: c_0 = sqrt(pi)(1 - sin(s)/s))."""
+    p0 = O.WaveletParams(L=2, s_theta=s, k=0, coeffs="quadrature")
+    c = O.sh_coeffs_A_quadrature(p0)
+    cc = math.cos(s / 2)
+    want = [math.sqrt(math.pi) * (1 - cc), math.sqrt(3 * math.pi) * math.sin(s / 2) ** 2 / 2,
+            math.sqrt(5 * math.pi) * (cc - cc ** 3) / 2]
+    assert np.allclose(c, want, rtol=0, atol=1e-14)
+    p1 = O.WaveletParams(L=0, s_theta=s, k=1, coeffs="quadrature")
+    assert abs(O.sh_coeffs_A_quadrature(p1)[0] - math.sqrt(math.pi) * (1 - math.sin(s) / s)) < 1e-14
+
+
+def test_bank_with_quadrature_coeffs():
+    """build_bank follows params.coeffs; both methods give admissible banks
+    that differ only by the fit's discretisation error."""
+    shape = (8, 10, 6)
+    n = inputs.icosahedral_orientations(1)
+    pl = O.WaveletParams(L=16, s_theta=0.7)
+    pq = O.WaveletParams(L=16, s_theta=0.7, coeffs="quadrature")
+    bl, bq = O.build_bank(shape, n, pl), O.build_bank(shape, n, pq)
+    assert np.array_equal(bq["c"], O.sh_coeffs_A_quadrature(pq))
+    assert not np.array_equal(bl["c"], bq["c"])
+    assert rel(bq["psi_hat"], bl["psi_hat"]) < 2e-2

@@ -1,0 +1,277 @@
+"""Host logic of the serving loop (continuous batching, admission by HBM
+footprint, bank cache, failure handling) driven through a fake executor on
+the CPU: every launch "runs" for a fixed time and doubles its volumes."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_1505_07690_amd.serve import AdmissionError, JobTimeout, Server
+
+
+class FakeBank:
+    def __init__(self, key):
+        self.key = key
+        V = int(np.prod(key[0]))
+        self.ws_bytes = 4 * V * 8
+        self.closed = False
+
+    def close(self):
+        self.closed = True
+
+
+class FakeHandle:
+    def __init__(self, jobs, t_end):
+        self.outs = [2.0 * j.volume for j in jobs]
+        self.t_end = t_end
+        self.n = len(jobs)
+
+
+class FakeExecutor:
+    def __init__(self, n_slots, run_s=0.02, fail_keys=()):
+        self.n_slots = n_slots
+        self.run_s = run_s
+        self.fail_keys = set(fail_keys)
+        self.lock = threading.Lock()
+        self.active = 0
+        self.max_active = 0
+        self.launches = []
+        self.built = []
+        self.freed = []
+
+    def input_ready(self, volume):
+        return None
+
+    def bank_bytes(self, key):
+        shape, n, L = key
+        if n not in (12, 42, 162):
+            raise ValueError("unsupported orientation count")
+        return int(np.prod(shape)) * n * 2
+
+    def build_bank(self, key, slot):
+        if key in self.fail_keys:
+            raise RuntimeError("bank build failed")
+        self.built.append(key)
+        return FakeBank(key)
+
+    def free_bank(self, bank):
+        self.freed.append(bank.key)
+        bank.close()
+
+    def job_bytes_estimate(self, key, B, op, dtype):
+        return self.job_bytes(key, FakeBank(key), B, op, dtype)
+
+    def job_bytes(self, key, bank, B, op, dtype):
+        shape, n, L = key
+        V = int(np.prod(shape))
+        return B * n * V * 8 + bank.ws_bytes
+
+    def launch(self, slot, bank, jobs):
+        for j in jobs:
+            if not np.all(np.isfinite(j.volume)):
+                raise ValueError("invalid volume")
+        with self.lock:
+            self.active += 1
+            self.max_active = max(self.max_active, self.active)
+        self.launches.append([j.id for j in jobs])
+        return FakeHandle(jobs, time.perf_counter() + self.run_s)
+
+    def done(self, h):
+        if time.perf_counter() >= h.t_end:
+            if h.outs is not None and not getattr(h, "_counted", False):
+                h._counted = True
+                with self.lock:
+                    self.active -= 1
+            return True
+        return False
+
+    def results(self, h):
+        return h.outs
+
+
+def vol(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape).astype(np.float32)
+
+
+def fp(shape, n):
+    """Footprint of one job plus its bank under the fake executor."""
+    V = int(np.prod(shape))
+    return n * V * 8 + 4 * V * 8 + V * n * 2
+
+
+def test_results_and_continuous_batching():
+    ex = FakeExecutor(1, run_s=0.05)
+    with Server(1 << 30, n_slots=1, max_batch=4, executor=ex) as s:
+        vs = [vol((8, 8, 8), i) for i in range(7)]
+        futs = [s.submit(vs[0], 42, 16)]
+        time.sleep(0.02)
+        futs += [s.submit(v, 42, 16) for v in vs[1:]]
+        for f, v in zip(futs, vs):
+            assert np.array_equal(f.result(timeout=5), 2 * v)
+        st = s.stats()
+    assert st["ok"] == 7 and st["max_batch"] > 1
+    # the first job ran alone; the ones that arrived meanwhile shared launches
+    assert ex.launches[0] == [0]
+    assert sum(len(b) for b in ex.launches) == 7 and max(len(b) for b in ex.launches) <= 4
+    assert st["bank_misses"] == 1 and st["bank_hits"] == len(ex.launches) - 1
+
+
+def test_mixed_keys_run_concurrently_on_slots():
+    ex = FakeExecutor(3, run_s=0.05)
+    with Server(1 << 30, n_slots=3, executor=ex) as s:
+        futs = [s.submit(vol(sh, i), n, L) for i, (sh, n, L) in
+                enumerate([((8, 8, 8), 42, 16), ((6, 8, 10), 12, 8), ((8, 8, 8), 162, 24)])]
+        for f in futs:
+            f.result(timeout=5)
+    assert ex.max_active == 3
+
+
+def test_admission_rejects_what_cannot_fit_and_keeps_serving():
+    ex = FakeExecutor(2)
+    budget = fp((8, 8, 8), 42) + 100
+    with Server(budget, n_slots=2, executor=ex) as s:
+        big = s.submit(vol((16, 16, 16), 0), 42, 16)
+        small = s.submit(vol((8, 8, 8), 1), 42, 16)
+        with pytest.raises(AdmissionError):
+            big.result(timeout=5)
+        assert np.array_equal(small.result(timeout=5), 2 * vol((8, 8, 8), 1))
+
+
+def test_memory_budget_serialises_jobs():
+    """Room for one bank and one job: jobs wait for memory, never run two at
+    a time, and all finish."""
+    ex = FakeExecutor(4, run_s=0.01)
+    budget = fp((8, 8, 8), 42) + 100
+    with Server(budget, n_slots=4, max_batch=1, executor=ex) as s:
+        futs = [s.submit(vol((8, 8, 8), i), 42, 16) for i in range(5)]
+        for f in futs:
+            f.result(timeout=5)
+        st = s.stats()
+    assert ex.max_active == 1
+    assert st["peak_bytes"] <= budget
+
+
+def test_invalid_job_fails_alone():
+    ex = FakeExecutor(2)
+    with Server(1 << 30, n_slots=2, max_batch=1, executor=ex) as s:
+        bad = vol((8, 8, 8), 0)
+        bad[0, 0, 0] = np.nan
+        fb = s.submit(bad, 42, 16)
+        fg = s.submit(vol((8, 8, 8), 1), 42, 16)
+        fo = s.submit(vol((8, 8, 8), 2), 7, 16)      # no such orientation set
+        fz = s.submit(vol((8, 8), 3), 42, 16)        # not a volume
+        fq = s.submit(vol((8, 8, 8), 4), 42, 16, op="nonsense")
+        with pytest.raises(ValueError):
+            fb.result(timeout=5)
+        with pytest.raises(ValueError):
+            fo.result(timeout=5)
+        with pytest.raises(ValueError):
+            fz.result(timeout=5)
+        with pytest.raises(ValueError):
+            fq.result(timeout=5)
+        fg.result(timeout=5)
+
+
+def test_bank_build_failure_fails_only_that_key():
+    ex = FakeExecutor(2, fail_keys=[((8, 8, 8), 162, 24)])
+    with Server(1 << 30, n_slots=2, executor=ex) as s:
+        f1 = s.submit(vol((8, 8, 8), 0), 162, 24)
+        f2 = s.submit(vol((8, 8, 8), 1), 42, 16)
+        with pytest.raises(RuntimeError, match="bank build failed"):
+            f1.result(timeout=5)
+        f2.result(timeout=5)
+
+
+def test_cancel_before_admission_and_timeout_while_pending():
+    ex = FakeExecutor(1, run_s=0.2)
+    with Server(1 << 30, n_slots=1, max_batch=1, executor=ex) as s:
+        first = s.submit(vol((8, 8, 8), 0), 42, 16)
+        time.sleep(0.02)
+        c = s.submit(vol((8, 8, 8), 1), 42, 16)
+        t = s.submit(vol((8, 8, 8), 2), 12, 8, timeout=0.05)
+        assert c.cancel()
+        with pytest.raises(JobTimeout):
+            t.result(timeout=5)
+        first.result(timeout=5)
+    assert all(1 not in b for b in ex.launches)
+
+
+def test_lru_bank_eviction_and_hit_rate():
+    """Room for one job and two cached banks: the least recently used idle
+    bank is dropped when a third key arrives."""
+    ex = FakeExecutor(1, run_s=0.001)
+    V = 512
+    job, bank = 42 * V * 8 + 4 * V * 8, V * 42 * 2
+    with Server(job + 2 * bank + 100, n_slots=1, executor=ex) as s:
+        for i, L in enumerate([8, 16, 8, 24, 8, 16]):
+            s.submit(vol((8, 8, 8), i), 42, L).result(timeout=5)
+        st = s.stats()
+    assert ex.freed == [((8, 8, 8), 42, 16), ((8, 8, 8), 42, 24)]
+    assert (st["bank_hits"], st["bank_misses"], st["bank_evictions"]) == (2, 4, 2)
+    assert st["peak_bytes"] <= job + 2 * bank + 100
+
+
+def test_oldest_job_is_not_starved():
+    """A large job that needs the whole budget is admitted before small jobs
+    that arrive after it has waited past the starvation limit."""
+    ex = FakeExecutor(2, run_s=0.03)
+    big_fp = fp((12, 12, 12), 42)
+    with Server(big_fp + 100, n_slots=2, max_batch=1, executor=ex, starvation_s=0.05) as s:
+        s.submit(vol((8, 8, 8), 0), 12, 8)
+        time.sleep(0.005)
+        big = s.submit(vol((12, 12, 12), 1), 42, 16)
+        late = []
+        for i in range(12):
+            time.sleep(0.01)
+            late.append(s.submit(vol((8, 8, 8), 2 + i), 12, 8))
+        big.result(timeout=5)
+        for f in late:
+            f.result(timeout=5)
+    ids = [b[0] for b in ex.launches]
+    # job 1 (the big one) runs before the small jobs submitted 0.05 s after it
+    assert ids.index(1) < ids.index(1 + 8)
+
+
+def test_close_drains_and_rejects_new_work():
+    ex = FakeExecutor(2, run_s=0.01)
+    s = Server(1 << 30, n_slots=2, executor=ex)
+    futs = [s.submit(vol((8, 8, 8), i), 42, 16) for i in range(4)]
+    s.close()
+    assert all(f.done() and not f.exception() for f in futs)
+    with pytest.raises(RuntimeError):
+        s.submit(vol((8, 8, 8), 9), 42, 16)
+
+
+def test_batch_bytes_caps_batches_of_large_jobs():
+    """Small jobs share launches; jobs whose batch would exceed batch_bytes
+    run one per launch."""
+    ex = FakeExecutor(1, run_s=0.03)
+    V = 512
+    one = 42 * V * 8 + 4 * V * 8
+    with Server(1 << 30, n_slots=1, max_batch=8, executor=ex, batch_bytes=3 * one) as s:
+        first = s.submit(vol((8, 8, 8), 0), 42, 16)
+        time.sleep(0.01)
+        futs = [s.submit(vol((8, 8, 8), 1 + i), 42, 16) for i in range(6)]
+        for f in [first] + futs:
+            f.result(timeout=5)
+    # job_bytes(n) = n * 42 V 8 + ws: at most 3 jobs fit in 3 * one
+    assert max(len(b) for b in ex.launches) == 3
+
+
+def test_waits_for_running_jobs_instead_of_evicting():
+    """When the running launch will free enough memory, a new key waits for
+    it rather than dropping a cached bank."""
+    ex = FakeExecutor(2, run_s=0.05)
+    V = 512
+    job, bank = 42 * V * 8 + 4 * V * 8, V * 42 * 2
+    with Server(2 * job + 2 * bank + 100, n_slots=2, max_batch=1, executor=ex) as s:
+        s.submit(vol((8, 8, 8), 0), 42, 8).result(timeout=5)      # bank A cached, idle
+        a = s.submit(vol((8, 8, 8), 1), 42, 16)                   # bank B + a running job
+        time.sleep(0.01)
+        b = s.submit(vol((8, 8, 8), 2), 42, 24)                   # bank C: fits only after `a`
+        a.result(timeout=5)
+        b.result(timeout=5)
+        st = s.stats()
+    assert st["bank_evictions"] == 0 and ex.freed == []
+    assert st["ok"] == 3 and st["errors"] == {}
