@@ -132,7 +132,10 @@ os3d_status os3d_bank_bytes(const int64_t dims[3], const double* orients, int32_
  * M[k] = sum_i psi_hat_i[k]^2 (Eq. 9, constants absorbed into kappa) into
  * bank_dev (os3d_bank_bytes bytes, caller-owned, must outlive the handle).
  * The contraction over spherical harmonics runs on the matrix cores.
- * Synchronises `stream` at the end.  *out receives a new handle. */
+ * Synchronises `stream` at the end.  *out receives a new handle.
+ * L > 62 returns OS3D_EUNSUPPORTED (the host-only calls accept L <= 64).
+ * A grid whose dims are all < 4 has no frequency in the normalisation band
+ * of kappa and returns OS3D_EINVAL. */
 os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_t n_orients,
                             const os3d_wavelet_params* p, void* bank_dev, size_t bank_bytes,
                             void* stream, os3d_bank** out);

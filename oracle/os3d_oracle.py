@@ -363,6 +363,9 @@ def band_kappa(raw_M, shape):
     wz, wy, wx, nyq = freq_grid(shape)
     rho = np.sqrt(wx * wx + wy * wy + wz * wz)
     band = (rho > 0) & (rho <= RHO_N / 2) & ~nyq
+    if not band.any():
+        # every dim < 4: no non-zero frequency within half the Nyquist radius
+        raise ValueError(f"the normalisation band of grid {shape} is empty (some dim must be >= 4)")
     return 1.0 / math.sqrt(float(np.mean(raw_M[band])))
 
 

@@ -306,6 +306,8 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
              void* stream);
 int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out, void* ws,
             bool divide_M, int nbmax, void* stream);
+template <int LM, int SM>
+void launch_plane(const PassArgs& a, int grid_y, hipStream_t st);
 int process4(const os3d_bank* b, const float* f, int batch, int phi_kind, float phi_p, float* f_out, void* ws,
              int nbmax, void* stream);
 

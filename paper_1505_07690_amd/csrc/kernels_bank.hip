@@ -26,13 +26,15 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBankPts = 256;   // frequency points per workgroup
 constexpr int kYStride = 272;   // LDS row stride (floats) of the K-chunk buffer
-constexpr int kColsPerSweep = 128;
+constexpr int kColBlocks = 3;                  // 16-column MFMA blocks per sweep
+constexpr int kColsPerSweep = 16 * kColBlocks;
+constexpr int kStageRegs = 12;                 // steering values prefetched per thread and chunk
 
 struct BankArgs {
   int layout;  // storage order of the frequency points (natural or four-step tiles)
   int Nz, Ny, Nx;
   long long V;
-  int L, Npad, n_rows;
+  int L, Npad, n_rows, maxpad;
   double t_inv;      // 1 / t of Eq. (10)
   int taylor_N;
   double dc_value;   // a_0 / sqrt(4 pi)
@@ -62,8 +64,9 @@ __device__ inline double radial_g(double rho2, double t_inv, int N) {
 }
 
 __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
-  extern __shared__ float Ybuf[];  // [kchunk_max][kYStride]
+  extern __shared__ float Ybuf[];  // [kchunk_max][kYStride], then [kchunk_max][kColsPerSweep]
   __shared__ double gsh[kBankPts];
+  __shared__ double Msh[kBankPts];
   __shared__ int dcsh[kBankPts];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -76,6 +79,7 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
   const double* blm = a.tab + nn + nn * nn;
   const int* koff = a.koff;
   const int* kpad = a.koff + nn;
+  float* Sbuf = Ybuf + a.maxpad * kYStride;  // this sweep's steering columns of chunk m
 
   // this thread's frequency point
   double ux = 0.0, uy = 0.0, uz = 1.0, g = 0.0;
@@ -98,16 +102,13 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
   }
   gsh[tid] = g;
   dcsh[tid] = dc;
-
-  double mh[4][4];
-  for (int r = 0; r < 4; ++r)
-    for (int i = 0; i < 4; ++i) mh[r][i] = 0.0;
+  Msh[tid] = 0.0;
 
   for (int c0 = 0; c0 < a.Npad; c0 += kColsPerSweep) {
     const int ncb = min(kColsPerSweep, a.Npad - c0) / 16;
-    floatx4 acc[4][8];
+    floatx4 acc[4][kColBlocks];
     for (int r = 0; r < 4; ++r)
-      for (int c = 0; c < 8; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int c = 0; c < kColBlocks; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     double cr = 1.0, ci = 0.0;  // (x + i y)^m of the unit frequency direction
     for (int m = 0; m <= L; ++m) {
@@ -118,6 +119,19 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
       }
       const int len = (m == 0) ? nn : 2 * (nn - m);
       const int pad = kpad[m];
+      // issue the loads of the chunk's steering rows (this sweep's columns)
+      // first, branch-free, so that they complete during the recursion
+      const float* Sm = a.S + (long long)koff[m] * a.Npad;
+      const int stotal = pad * kColsPerSweep;
+      float sv[kStageRegs];
+#pragma unroll
+      for (int u = 0; u < kStageRegs; ++u) {
+        const int idx = u * kBankPts + tid;
+        const int kr = idx / kColsPerSweep, cc = idx - kr * kColsPerSweep;
+        const bool ok = idx < stotal && c0 + cc < a.Npad;
+        const float v = Sm[ok ? (long long)kr * a.Npad + c0 + cc : 0];
+        sv[u] = ok ? v : 0.f;
+      }
       // generate chunk m: Q_l^m for l = m..L (sinus power factored out)
       {
         double q2 = 0.0, q1 = qmm[m];
@@ -141,28 +155,40 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
         }
         for (int kk = len; kk < pad; ++kk) Ybuf[kk * kYStride + tid] = 0.f;
       }
+      // stage the steering rows in LDS (rows past kStageRegs * 256 values,
+      // needed only for L > 31, are loaded here)
+#pragma unroll
+      for (int u = 0; u < kStageRegs; ++u)
+        if (u * kBankPts + tid < stotal) Sbuf[u * kBankPts + tid] = sv[u];
+      for (int idx = kStageRegs * kBankPts + tid; idx < stotal; idx += kBankPts) {
+        const int kr = idx / kColsPerSweep, cc = idx - kr * kColsPerSweep;
+        Sbuf[idx] = (c0 + cc < a.Npad) ? Sm[(long long)kr * a.Npad + c0 + cc] : 0.f;
+      }
       __syncthreads();
-      const float* Sm = a.S + (long long)koff[m] * a.Npad + c0;
       for (int k0 = 0; k0 < pad; k0 += 4) {
         const int kr = k0 + (lane >> 4);
-        float af[4];
+        float af[4], bf[kColBlocks];
+#pragma unroll
         for (int r = 0; r < 4; ++r) af[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
-        const float* Sr = Sm + (long long)kr * a.Npad + (lane & 15);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          if (c < ncb) {
-            float bf = Sr[c * 16];
+        for (int c = 0; c < kColBlocks; ++c) bf[c] = Sbuf[kr * kColsPerSweep + c * 16 + (lane & 15)];
+        // all column blocks, also past Npad (zero columns): no branch between the MFMAs
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[r], bf, acc[r][c], 0, 0, 0);
-          }
-        }
+        for (int c = 0; c < kColBlocks; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[r], bf[c], acc[r][c], 0, 0, 0);
       }
       __syncthreads();
     }
 
     // epilogue: psi_raw = g * h (DC: isotropic), bank rows, FP64 sum of squares
+    double mh[4][4];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) mh[r][i] = 0.0;
+#pragma unroll
+    for (int c = 0; c < kColBlocks; ++c) {
       if (c >= ncb) continue;
       const int col = c0 + c * 16 + (lane & 15);
       const bool colok = col < a.n_rows;
@@ -179,27 +205,22 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
         }
       }
     }
-  }
-
-  // sum over the 16 lanes that share (lane >> 4): fixed xor tree
+    // sum over the 16 lanes that share (lane >> 4): fixed xor tree, then
+    // into the point's running sum (one owner lane per point)
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double s = mh[r][i];
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
-      s += __shfl_xor(s, 4);
-      s += __shfl_xor(s, 8);
-      mh[r][i] = s;
-    }
-  if ((lane & 15) == 0) {
     for (int r = 0; r < 4; ++r)
+#pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const long long gp = p0 + wave * 64 + r * 16 + 4 * (lane >> 4) + i;
-        if (gp < a.V) a.Mh[gp] = mh[r][i];
+        double s = mh[r][i];
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        s += __shfl_xor(s, 8);
+        if ((lane & 15) == 0) Msh[wave * 64 + r * 16 + 4 * (lane >> 4) + i] += s;
       }
   }
+  __syncthreads();
+  if (valid) a.Mh[p] = Msh[tid];
 }
 
 // S: k -> -k mod N on every axis, on storage positions.
@@ -406,7 +427,8 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   using std::max;
   KLayout kl = k_layout(L);
   for (int m = 0; m <= L; ++m) maxpad = max(maxpad, kl.pad[m]);
-  size_t lds = (size_t)maxpad * kYStride * sizeof(float);
+  a.maxpad = maxpad;
+  size_t lds = (size_t)maxpad * (kYStride + kColsPerSweep) * sizeof(float);
   const long long nblk = (b->V + kBankPts - 1) / kBankPts;
   if (hipFuncSetAttribute((const void*)k_bank_synth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
       hipSuccess) {

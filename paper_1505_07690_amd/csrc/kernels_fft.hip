@@ -458,6 +458,24 @@ static int run_pass(int kid, double alg, const PassArgs& a, int grid_y, hipStrea
   return check_launch(kKernelNames[kid]);
 }
 
+// Whole-plane pass of the two-pass path (kernels_plane.hip).
+template <int LM, int SM>
+static int run_plane(int kid, double alg, const PassArgs& a, int grid_y, hipStream_t st) {
+  void* tok = prof_start(st);
+  launch_plane<LM, SM>(a, grid_y, st);
+  prof_stop(tok, st, kid, alg, 0.0);
+  return check_launch(kKernelNames[kid]);
+}
+
+// Arguments of a whole-plane pass (the x twiddles serve both plane axes).
+static PassArgs plane_args(const os3d_bank* b, float sgn, int nb) {
+  PassArgs a = {};
+  setup_axis(b, 2, a);
+  a.sgn = sgn;
+  a.nb = nb;
+  return a;
+}
+
 // Algorithmic score bytes of one launch over nb stored rows: every stored
 // row stands for one orientation, or two with its antipode.
 static double score_bytes(const os3d_bank* b, const PassArgs& a, int nb, size_t ubytes) {
@@ -494,6 +512,19 @@ size_t workspace_bytes(const os3d_bank* b) {
 // forward DFT of one real volume into F (three passes, in place after the first)
 static int dft_real_volume(const os3d_bank* b, const float* f, float2* F, hipStream_t st) {
   int rc;
+  if (b->plane) {
+    PassArgs a = plane_args(b, -1.f, 1);
+    a.src_r = f;
+    a.dst_c = F;
+    if ((rc = run_plane<LM_REAL, SM_C>(kProfDftFirst, 4.0 * b->V, a, 1, st))) return rc;
+    PassArgs c = {};
+    setup_axis(b, 0, c);
+    c.sgn = -1.f;
+    c.nb = 1;
+    c.src_c = F;
+    c.dst_c = F;
+    return run_pass<LM_C, SM_C>(kProfDftLast, 0.0, c, 1, st);
+  }
   PassArgs a = {};
   setup_axis(b, 2, a);
   a.sgn = -1.f;
@@ -553,6 +584,21 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
         hipLaunchKernelGGL(k_scales, dim3(nb), dim3(256), 0, st, partial, (int)tiles, z, dtype, sc);
         prof_stop(tok, st, kProfScales, 0.0, 0.0);
         if ((rc = check_launch("k_scales"))) return rc;
+      }
+      if (b->plane) {
+        PassArgs x = plane_args(b, 1.f, nb);
+        for (int j = 0; j < nb; ++j) {
+          x.oa[j] = z.oa[j];
+          x.ob[j] = z.ob[j];
+        }
+        x.src_c = T;
+        x.src_stride = V;
+        x.Uout = Ub;
+        x.dtype = dtype;
+        x.scales = quant ? sc : nullptr;
+        x.out_scale = 1.f / (float)V;
+        if ((rc = run_plane<LM_C, SM_UOUT>(kProfFwdLast, score_bytes(b, z, nb, ubytes), x, nb, st))) return rc;
+        continue;
       }
       PassArgs y = {};
       setup_axis(b, 1, y);
@@ -614,16 +660,20 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
       x.scales = (dtype == OS3D_C64) ? nullptr : sc;
       x.dst_c = T;
       x.dst_stride = V;
-      if ((rc = run_pass<LM_UIN, SM_C>(kProfRecFirst, score_bytes(b, x, nb, ubytes), x, nb, st))) return rc;
-      PassArgs y = {};
-      setup_axis(b, 1, y);
-      y.sgn = -1.f;
-      y.nb = nb;
-      y.src_c = T;
-      y.src_stride = V;
-      y.dst_c = T;
-      y.dst_stride = V;
-      if ((rc = run_pass<LM_C, SM_C>(kProfRecMid, 0.0, y, nb, st))) return rc;
+      if (b->plane) {  // x was set up on the x axis: the plane pass's twiddles
+        if ((rc = run_plane<LM_UIN, SM_C>(kProfRecFirst, score_bytes(b, x, nb, ubytes), x, nb, st))) return rc;
+      } else {
+        if ((rc = run_pass<LM_UIN, SM_C>(kProfRecFirst, score_bytes(b, x, nb, ubytes), x, nb, st))) return rc;
+        PassArgs y = {};
+        setup_axis(b, 1, y);
+        y.sgn = -1.f;
+        y.nb = nb;
+        y.src_c = T;
+        y.src_stride = V;
+        y.dst_c = T;
+        y.dst_stride = V;
+        if ((rc = run_pass<LM_C, SM_C>(kProfRecMid, 0.0, y, nb, st))) return rc;
+      }
       PassArgs z = {};
       setup_axis(b, 0, z);
       z.sgn = -1.f;
@@ -647,6 +697,14 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
     z.divide = divide_M ? 1 : 0;
     z.dst_c = X;
     if ((rc = run_pass<LM_DIVM, SM_C>(kProfInvFirst, 0.0, z, 1, st))) return rc;
+    if (b->plane) {
+      PassArgs x = plane_args(b, 1.f, 1);
+      x.src_c = X;
+      x.dst_r = f_out + (long long)bi * V;
+      x.out_scale = 1.f / (float)V;
+      if ((rc = run_plane<LM_C, SM_REAL>(kProfInvLast, 4.0 * b->V, x, 1, st))) return rc;
+      continue;
+    }
     PassArgs y = {};
     setup_axis(b, 1, y);
     y.sgn = 1.f;
@@ -698,6 +756,35 @@ int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, 
       z.dst_c = T;
       z.dst_stride = V;
       if ((rc = run_pass<LM_MULBANK, SM_C>(kProfFwdFirst, 0.0, z, nb, st))) return rc;
+      if (b->plane) {
+        PassArgs x = z;
+        setup_axis(b, 2, x);
+        x.src_c = T;
+        x.src_stride = V;
+        x.dst_c = Z;
+        x.dst_stride = V;
+        x.out_scale = 1.f / (float)V;
+        x.phi_kind = phi_kind;
+        x.phi_p = phi_p;
+        if ((rc = run_plane<LM_C, SM_PHI>(kProfFwdLast, 0.0, x, nb, st))) return rc;
+        PassArgs u = z;
+        setup_axis(b, 2, u);
+        u.sgn = -1.f;
+        u.src_c = Z;
+        u.src_stride = V;
+        u.dst_c = T;
+        u.dst_stride = V;
+        if ((rc = run_plane<LM_C, SM_C>(kProfRecFirst, 0.0, u, nb, st))) return rc;
+        PassArgs w = u;
+        setup_axis(b, 0, w);
+        w.src_c = T;
+        w.psi = b->d.psi;
+        w.dst_c = X;
+        w.dst_stride = 0;
+        w.accumulate = (r0 > 0) ? 1 : 0;
+        if ((rc = run_pass<LM_C, SM_ACCUM>(kProfRecLast, 0.0, w, 1, st))) return rc;
+        continue;
+      }
       PassArgs y = z;
       setup_axis(b, 1, y);
       y.src_c = T;
@@ -744,6 +831,14 @@ int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, 
     z.divide = 1;
     z.dst_c = X;
     if ((rc = run_pass<LM_DIVM, SM_C>(kProfInvFirst, 0.0, z, 1, st))) return rc;
+    if (b->plane) {
+      PassArgs x = plane_args(b, 1.f, 1);
+      x.src_c = X;
+      x.dst_r = f_out + (long long)bi * V;
+      x.out_scale = 1.f / (float)V;
+      if ((rc = run_plane<LM_C, SM_REAL>(kProfInvLast, 4.0 * b->V, x, 1, st))) return rc;
+      continue;
+    }
     PassArgs y = {};
     setup_axis(b, 1, y);
     y.sgn = 1.f;

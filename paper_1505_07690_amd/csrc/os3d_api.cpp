@@ -168,6 +168,12 @@ os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_
   if ((rc = check_orients(orients, n))) return (os3d_status)rc;
   if ((rc = check_params(p))) return (os3d_status)rc;
   if (!bank_dev || !out) return (os3d_status)fail(OS3D_EINVAL, "bank_dev or out is NULL");
+  if (p->L > kMaxBankL)
+    return (os3d_status)fail(OS3D_EUNSUPPORTED, "bank synthesis supports L <= " + std::to_string(kMaxBankL));
+  // kappa averages M over {k != 0, rho <= rho_N / 2, off the Nyquist planes}:
+  // the axis frequency 2 pi / N is inside only for N >= 4
+  if (std::max(dims[0], std::max(dims[1], dims[2])) < 4)
+    return (os3d_status)fail(OS3D_EINVAL, "the normalisation band is empty: some dim must be >= 4");
   os3d_bank* b = new (std::nothrow) os3d_bank();
   if (!b) return (os3d_status)fail(OS3D_ENOMEM, "host allocation failed");
   for (int d = 0; d < 3; ++d) b->dims[d] = dims[d];
@@ -180,8 +186,9 @@ os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_
   b->Npad = (b->n_unique + 15) / 16 * 16;
   // 256^3 volumes take the two-pass transform and its frequency tiles
   b->layout = (dims[0] == 256 && dims[1] == 256 && dims[2] == 256) ? 1 : 0;
+  b->plane = (b->layout == 0 && dims[1] == dims[2] && (dims[2] == 64 || dims[2] == 128)) ? 1 : 0;
   if (const char* e = std::getenv("OS3D_THREE_PASS"))
-    if (e[0] == '1') b->layout = 0;
+    if (e[0] == '1') b->layout = b->plane = 0;
   const BankLayout lay = layout(dims, b->n_unique, p->L);
   if (bank_bytes_given < lay.total) {
     delete b;

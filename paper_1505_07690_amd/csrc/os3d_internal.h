@@ -10,6 +10,10 @@
 
 namespace os3d {
 
+// Largest SH order of the device bank synthesis: its LDS holds the largest
+// K-chunk (2L values, padded to 4) for 256 points plus the staged steering rows.
+constexpr int kMaxBankL = 62;
+
 constexpr int kMaxL = 64;
 constexpr int kMaxDim = 4096;
 constexpr int kMaxStages = 14;
@@ -83,6 +87,7 @@ struct os3d_bank {
   int n_unique;
   int paired;
   int layout;                 // frequency storage order: 0 natural, 1 four-step tiles of 256^3
+  int plane;                  // natural order with Ny = Nx in {64, 128}: z-line pass + whole-plane pass
   int L;
   int Npad;
   int K;

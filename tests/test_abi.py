@@ -97,7 +97,7 @@ def test_errors_are_status_codes():
     tiny = (ctypes.c_int64 * 3)(8, 1, 8)
     assert L.os3d_bank_bytes(tiny, n.ctypes.data, 12, ctypes.byref(good), ctypes.byref(nbytes)) == -1
     for field, val in [("L", -1), ("L", 65), ("s_theta", 0.0), ("k", -1), ("taylor_N", -2), ("gamma", 1.0),
-                       ("gamma", 0.0), ("eps", 0.0), ("variant", 7)]:
+                       ("gamma", 0.0), ("eps", 0.0), ("variant", 7), ("coeffs", 2)]:
         p = os3d.make_params(L=8, s_theta=1.3)
         setattr(p, field, val)
         assert L.os3d_bank_bytes(dims, n.ctypes.data, 12, ctypes.byref(p), ctypes.byref(nbytes)) == -1, field
@@ -109,6 +109,15 @@ def test_errors_are_status_codes():
     # build with a NULL device buffer is rejected before any device call
     h = ctypes.c_void_p()
     assert L.os3d_build_bank(dims, n.ctypes.data, 12, ctypes.byref(good), None, 0, None, ctypes.byref(h)) == -1
+    # the device synthesis stops at L = 62 (before touching the buffer)
+    high = os3d.make_params(L=63, s_theta=1.3)
+    fake = ctypes.c_void_p(8)
+    assert L.os3d_build_bank(dims, n.ctypes.data, 12, ctypes.byref(high), fake, 1 << 40, None, ctypes.byref(h)) == -3
+    assert b"L <= 62" in L.os3d_last_error()
+    # a grid with an empty normalisation band (every dim < 4)
+    small = (ctypes.c_int64 * 3)(2, 3, 3)
+    assert L.os3d_build_bank(small, n.ctypes.data, 12, ctypes.byref(good), fake, 1 << 40, None, ctypes.byref(h)) == -1
+    assert b"band is empty" in L.os3d_last_error()
     # compute calls with a NULL bank
     assert L.os3d_forward(None, None, 1, None, 0, None, None, 0, None) == -1
     assert L.os3d_reconstruct(None, None, 0, None, 1, None, None, 0, None) == -1

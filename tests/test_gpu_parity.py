@@ -67,6 +67,15 @@ CASES = {
     "quad_k3": lambda: ((12, 16, 10), inputs.icosahedral_orientations(1),
                         O.WaveletParams(L=12, s_theta=0.5, k=3, coeffs="quadrature"),
                         inputs.tubes((12, 16, 10), 2, 1.2, 0.1, 0, 12)),
+    # the smallest grid with a normalisation band: radices 2, 3, 4, mostly Nyquist planes
+    "tiny234": lambda: ((2, 3, 4), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
+                        inputs.tubes((2, 3, 4), 1, 1.0, 0.1, 0, 13)),
+    # the longest supported axis (4096 = 2^12) through the LDS Stockham kernel, odd sizes beside it
+    "axis4096": lambda: ((2, 3, 4096), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
+                         inputs.tubes((2, 3, 4096), 2, 1.0, 0.1, 0, 14)),
+    # whole-plane path: 128 x 128 planes over a z axis of 20 (radix 4 x 5 in the z pass)
+    "plane128": lambda: ((20, 128, 128), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
+                         inputs.tubes((20, 128, 128), 3, 1.5, 0.1, 0, 15)),
     # small N with radix-2 only and a long axis
     "long4x6x64": lambda: ((4, 6, 64), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                            inputs.tubes((4, 6, 64), 2, 1.0, 0.1, 0, 8)),
@@ -184,15 +193,17 @@ def test_antipodal_pairs_are_conjugate(torch_dev):
     assert torch_dev.equal(U[j], torch_dev.conj(U).resolve_conj())
 
 
-@pytest.mark.parametrize("fmt,bound", [("bf16", 4e-3), ("fp16", 5e-4)])
-def test_reduced_precision_storage(torch_dev, fmt, bound):
+@pytest.mark.parametrize("fmt,bound,shape", [("bf16", 4e-3, (32, 32, 32)), ("fp16", 5e-4, (32, 32, 32)),
+                                             ("bf16", 4e-3, (24, 64, 64)), ("fp16", 5e-4, (24, 64, 64))],
+                         ids=["bf16_three_pass", "fp16_three_pass", "bf16_plane", "fp16_plane"])
+def test_reduced_precision_storage(torch_dev, fmt, bound, shape):
     """16-bit score storage with per-orientation power-of-two scales: error of
-    U and of the reconstruction against the FP64 oracle."""
+    U and of the reconstruction against the FP64 oracle (three-pass path and
+    z-line + whole-plane path)."""
     from paper_1505_07690_amd import os3d
-    shape = (32, 32, 32)
     n = inputs.icosahedral_orientations(1)
     p = _oracle_params(16, 42)
-    vol = inputs.config_volume("A")
+    vol = inputs.config_volume("A") if shape == (32, 32, 32) else inputs.tubes(shape, 3, 1.5, 0.1, 0, 16)
     ob, gb, f = _case(shape, n, p, vol)
     Uq, sc = os3d.forward(f, gb, dtype=fmt)
     s = sc.cpu().numpy()
@@ -235,3 +246,25 @@ def test_process_parity(case, phi, power):
     got = os3d.process(case["f"], case["gb"], phi, power).cpu().numpy()
     want = O.process(case["vol"].astype(np.float64), case["ob"], phi, power)
     assert rel(got, want) < TOL
+
+
+def test_three_pass_path_on_plane_shapes(torch_dev, monkeypatch):
+    """Shapes with 64^2 or 128^2 planes take the z-line + whole-plane path;
+    the three-pass path (forced for this bank) gives the same transform."""
+    from paper_1505_07690_amd import os3d
+    shape = (16, 64, 64)
+    n = inputs.icosahedral_orientations(0)
+    p = _oracle_params(8, 12)
+    vol = inputs.tubes(shape, 3, 1.5, 0.1, 0, 17)
+    ob = O.build_bank(shape, n, p)
+    f = torch_dev.from_numpy(vol).cuda()
+    monkeypatch.setenv("OS3D_THREE_PASS", "1")
+    g3 = os3d.Bank(shape, n, p)
+    monkeypatch.delenv("OS3D_THREE_PASS")
+    g2 = os3d.Bank(shape, n, p)
+    Uo = O.forward(vol.astype(np.float64), ob)
+    ro = O.reconstruct(Uo, ob)
+    for gb in (g3, g2):
+        U, _ = os3d.forward(f, gb)
+        assert rel(U.cpu().numpy(), Uo) < TOL
+        assert rel(os3d.reconstruct(U, gb).cpu().numpy(), ro) < TOL

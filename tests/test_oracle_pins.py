@@ -604,3 +604,14 @@ def test_bank_with_quadrature_coeffs():
     assert np.array_equal(bq["c"], O.sh_coeffs_A_quadrature(pq))
     assert not np.array_equal(bl["c"], bq["c"])
     assert rel(bq["psi_hat"], bl["psi_hat"]) < 2e-2
+
+
+def test_empty_normalisation_band_is_an_error():
+    """Grids with every dim < 4 have no frequency with 0 < rho <= rho_N / 2
+    off the Nyquist planes, so kappa is undefined; (2, 3, 4) has one."""
+    n = inputs.icosahedral_orientations(0)
+    p = O.WaveletParams(L=4, s_theta=inputs.s_theta_for(12))
+    with pytest.raises(ValueError, match="band"):
+        O.build_bank((2, 3, 3), n, p)
+    b = O.build_bank((2, 3, 4), n, p)
+    assert np.isfinite(b["kappa"]) and b["kappa"] > 0
