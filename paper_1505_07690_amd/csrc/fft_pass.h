@@ -135,6 +135,19 @@ __device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long 
   }
 }
 
+// Phi of processing via scores applied to one transformed value v (times
+// out_scale = 1/V), times 2 for a stored antipodal pair: for real f the pair
+// contributes Phi(U_n) + conj(Phi(U_-n)) = 2 Phi(U_n) to the reconstruction.
+__device__ __forceinline__ float2 phi_apply(const PassArgs& a, int j, float2 v) {
+  const float2 u = cscale(v, a.out_scale);
+  const float mult = (a.ob[j] >= 0) ? 2.f : 1.f;
+  if (a.phi_kind == 1) {
+    const float m = sqrtf(u.x * u.x + u.y * u.y);
+    return cscale(u, (m > 0.f) ? mult * powf(m, a.phi_p - 1.f) : 0.f);
+  }
+  return cscale(u, mult);
+}
+
 // Fused last-pass store of element g for pair slot j (SM_ACCUM adds into acc).
 template <int SM, int DT = OS3D_C64>
 __device__ __forceinline__ void store_elem(const PassArgs& a, int j, long long g, float2 v, float2& acc) {
@@ -150,14 +163,7 @@ __device__ __forceinline__ void store_elem(const PassArgs& a, int j, long long g
     const float p = a.psi[(long long)a.rows[j] * a.V + g];
     acc = make_float2(acc.x + p * v.x, acc.y + p * v.y);
   } else if constexpr (SM == SM_PHI) {
-    const float2 u = cscale(v, a.out_scale);
-    const float mult = (a.ob[j] >= 0) ? 2.f : 1.f;
-    float f = mult;
-    if (a.phi_kind == 1) {
-      const float m = sqrtf(u.x * u.x + u.y * u.y);
-      f = (m > 0.f) ? mult * powf(m, a.phi_p - 1.f) : 0.f;
-    }
-    a.dst_c[j * a.dst_stride + g] = cscale(u, f);
+    a.dst_c[j * a.dst_stride + g] = phi_apply(a, j, v);
   } else {  // SM_REAL
     a.dst_r[g] = v.x * a.out_scale;
   }
@@ -255,22 +261,10 @@ __device__ __forceinline__ void store_k(const PassArgs& a, int j, long long g0, 
 #pragma unroll
     for (int r = 0; r < K; ++r) acc[r] = make_float2(acc[r].x + ps[r] * v[r].x, acc[r].y + ps[r] * v[r].y);
   } else if constexpr (SM == SM_PHI) {
-    // the pointwise map of the score, stored as the reconstruction's input
-    // for the pair: Phi(U_n) + conj(Phi(U_-n)) = 2 Phi(U_n) for real f
+    // the reconstruction's input for the pair (phi_apply)
     float2* p = a.dst_c + j * a.dst_stride;
-    const float mult = (a.ob[j] >= 0) ? 2.f : 1.f;
-    if (a.phi_kind == 1) {
 #pragma unroll
-      for (int r = 0; r < K; ++r) {
-        const float2 u = cscale(v[r], a.out_scale);
-        const float m = sqrtf(u.x * u.x + u.y * u.y);
-        const float f = (m > 0.f) ? mult * powf(m, a.phi_p - 1.f) : 0.f;
-        p[g0 + r * d] = cscale(u, f);
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < K; ++r) p[g0 + r * d] = cscale(v[r], mult * a.out_scale);
-    }
+    for (int r = 0; r < K; ++r) p[g0 + r * d] = phi_apply(a, j, v[r]);
   } else {  // SM_REAL
 #pragma unroll
     for (int r = 0; r < K; ++r) a.dst_r[g0 + r * d] = v[r].x * a.out_scale;
@@ -308,6 +302,7 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
             bool divide_M, int nbmax, void* stream);
 template <int LM, int SM>
 void launch_plane(const PassArgs& a, int grid_y, hipStream_t st);
+void launch_plane_phi(const PassArgs& a, int grid_y, hipStream_t st);
 int process4(const os3d_bank* b, const float* f, int batch, int phi_kind, float phi_p, float* f_out, void* ws,
              int nbmax, void* stream);
 

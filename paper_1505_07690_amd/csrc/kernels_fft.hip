@@ -728,7 +728,9 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
 // three-pass path (see process4 for the structure).
 int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, float phi_p, float* f_out, void* ws,
                    void* stream) {
-  const int nbp = std::max(1, pair_batch(b) / 2);
+  // the plane path transforms in place (F, X and one volume per pair); the
+  // others keep the reconstruction's input in a second volume per pair
+  const int nbp = b->plane ? pair_batch(b) : std::max(1, pair_batch(b) / 2);
   if (b->layout == kLayoutFour256) return process4(b, f, batch, phi_kind, phi_p, f_out, ws, nbp, stream);
   hipStream_t st = (hipStream_t)stream;
   const long long V = b->V;
@@ -756,28 +758,27 @@ int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, 
       z.dst_c = T;
       z.dst_stride = V;
       if ((rc = run_pass<LM_MULBANK, SM_C>(kProfFwdFirst, 0.0, z, nb, st))) return rc;
-      if (b->plane) {
+      if (b->plane) {  // inverse plane DFT, Phi, forward plane DFT in one kernel, in place
         PassArgs x = z;
         setup_axis(b, 2, x);
         x.src_c = T;
         x.src_stride = V;
-        x.dst_c = Z;
+        x.dst_c = T;
         x.dst_stride = V;
         x.out_scale = 1.f / (float)V;
         x.phi_kind = phi_kind;
         x.phi_p = phi_p;
-        if ((rc = run_plane<LM_C, SM_PHI>(kProfFwdLast, 0.0, x, nb, st))) return rc;
-        PassArgs u = z;
-        setup_axis(b, 2, u);
-        u.sgn = -1.f;
-        u.src_c = Z;
-        u.src_stride = V;
-        u.dst_c = T;
-        u.dst_stride = V;
-        if ((rc = run_plane<LM_C, SM_C>(kProfRecFirst, 0.0, u, nb, st))) return rc;
-        PassArgs w = u;
+        {
+          void* tok = prof_start(st);
+          launch_plane_phi(x, nb, st);
+          prof_stop(tok, st, kProfFwdLast, 0.0, 0.0);
+          if ((rc = check_launch("k_plane_phi"))) return rc;
+        }
+        PassArgs w = z;
         setup_axis(b, 0, w);
+        w.sgn = -1.f;
         w.src_c = T;
+        w.src_stride = V;
         w.psi = b->d.psi;
         w.dst_c = X;
         w.dst_stride = 0;

@@ -215,6 +215,74 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
   for (int k2 = 0; k2 < 16; ++k2) T[((long long)(k2 * 64 + kxb) * 16) * 1024 + o] = u[k2];
 }
 
+// Natural side of both directions, for processing via scores: inverse T
+// tile (k2, zb) -> step C and the inverse x DFT -> the scores of rows
+// y = k2 + 16 k1 of four z planes -> Phi -> the forward x DFT and step A
+// (n1 = k2, n2 = k1) -> forward T.  After the inverse x DFT a thread holds
+// x = s + 16 r of row (g, k1), which is exactly what the forward pass loads
+// into that thread, so the scores never leave the registers.
+__global__ __launch_bounds__(k4Threads) void k4_nat_phi(PassArgs a) {
+  __shared__ float2 lds[4 * k4Sub];
+  __shared__ float2 twl[256];  // exp(-2 pi i m / 256); conjugated for the inverse direction
+  const int t = threadIdx.x;
+  const int tile = blockIdx.x, c = tile >> 6, zb = tile & 63;
+  const int j = blockIdx.y;
+  for (int i = t; i < 256; i += k4Threads) twl[i] = a.tw[i];
+  const float2* T = a.src_c + (long long)j * a.src_stride + (long long)tile * 16 * 1024;
+  float2 v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = T[q * 1024 + t];
+  dft16(v, 1.f);  // over n1 -> k1
+  {
+    const int g = (t >> 2) & 3, kx = (t >> 4) * 4 + (t & 3);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) lds[g * k4Sub + k1 * k4LS + pad4(kx)] = v[k1];
+  }
+  __syncthreads();
+  const int g = t >> 8, k1 = (t >> 4) & 15, s = t & 15;
+  float2* S = lds + g * k4Sub + k1 * k4LS;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+  dft16(v, 1.f);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], cconj(twl[s * r]));
+  dft16(v, 1.f);
+  // V U at (z = 4 zb + g, y = 16 k1 + c, x = s + 16 r) -> Phi
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = phi_apply(a, j, v[r]);
+  // forward direction on the same rows
+  dft16(v, -1.f);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
+#pragma unroll
+  for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
+  dft16(v, -1.f);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) S[pad4(s + 16 * r)] = v[r];
+  __syncthreads();
+  const int zz = (t >> 2) & 3, kxx = t & 3, kxb = t >> 4, kx = kxb * 4 + kxx;
+  float2 u[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) u[q] = lds[zz * k4Sub + q * k4LS + pad4(kx)];
+  dft16(u, -1.f);
+#pragma unroll
+  for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[c * k2]);
+  float2* Tf = a.dst_c + (long long)j * a.dst_stride;
+  const long long o = (long long)c * 1024 + (4 * zb + zz) * 4 + kxx;
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) Tf[((long long)(k2 * 64 + kxb) * 16) * 1024 + o] = u[k2];
+}
+
 // Frequency side of the forward direction: T tile (k2, kxb) -> Phi tile
 // (kxb, n1 = k2).  Step C over n1, then the z DFT (two stages), then the
 // fused store (F) or the weighted orientation sum over the pair batch (X).
@@ -432,9 +500,10 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
 }
 
 // Processing via scores, Eq. (23) with the stabilised inverse: per pair
-// batch the forward transform's last pass applies Phi and writes the
-// reconstruction's input 2 Phi(U_n) (the score itself never reaches memory),
-// then the two forward-direction passes accumulate the orientation sum.
+// batch, the frequency-side pass of the inverse direction, then one
+// natural-side kernel for both directions with Phi in registers (the scores
+// never reach memory), then the frequency-side accumulation of the
+// orientation sum.
 int process4(const os3d_bank* b, const float* f, int batch, int phi_kind, float phi_p, float* f_out, void* ws,
              int nbmax, void* stream) {
   hipStream_t st = (hipStream_t)stream;
@@ -480,25 +549,14 @@ int process4(const os3d_bank* b, const float* f, int batch, int phi_kind, float 
       x.phi_p = phi_p;
       {
         void* tok = prof_start(st);
-        hipLaunchKernelGGL((k4_inv_nat<SM_PHI, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        hipLaunchKernelGGL(k4_nat_phi, dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfFwdLast, 0.0, 0.0);
-        if ((rc = check("k4_inv_nat"))) return rc;
+        if ((rc = check("k4_nat_phi"))) return rc;
       }
-      PassArgs y = base_args(b, -1.f);
-      y.nb = nb;
-      for (int jj = 0; jj < nb; ++jj) y.rows[jj] = z.rows[jj];
-      y.src_c = Z;
-      y.src_stride = V;
-      y.dst_c = T;
-      y.dst_stride = V;
-      {
-        void* tok = prof_start(st);
-        hipLaunchKernelGGL((k4_fwd_nat<LM_C, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, y);
-        prof_stop(tok, st, kProfRecFirst, 0.0, 0.0);
-        if ((rc = check("k4_fwd_nat"))) return rc;
-      }
-      PassArgs w = y;
-      w.src_c = T;
+      PassArgs w = base_args(b, -1.f);
+      w.nb = nb;
+      for (int jj = 0; jj < nb; ++jj) w.rows[jj] = z.rows[jj];
+      w.src_c = Z;
       w.src_stride = V;
       w.psi = b->d.psi;
       w.dst_c = X;

@@ -14,7 +14,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
+#include <unordered_set>
 
 #include "fft_pass.h"
 
@@ -26,7 +28,10 @@ struct PlaneCfg {
   static constexpr int TL = NP / 16;      // threads per line
   static constexpr int R2 = NP / 16;      // second-stage radix
   static constexpr int B2 = 16 / R2;      // second-stage butterflies per thread
-  static constexpr int RS = NP + NP / 16 + 1;  // LDS row stride (float2)
+  // LDS row stride (float2): 8 (NP = 128) or 16 (NP = 64) rows of a wave
+  // start on distinct bank groups, so the row stages run at the minimum two
+  // passes per wave-wide access
+  static constexpr int RS = NP + NP / 16;
 };
 
 __device__ __forceinline__ int ppad(int x) { return x + (x >> 4); }
@@ -146,21 +151,92 @@ struct PlaneIn<LM_UIN, DT> {
   }
 };
 
+// x lines of the plane in LDS, in place: thread (row y, slot s).  The
+// caller synchronises before and after.
+template <int NP, bool INV>
+__device__ __forceinline__ void plane_rows(float2* P, const float2* twl, int t) {
+  using C = PlaneCfg<NP>;
+  constexpr float sg = INV ? 1.f : -1.f;
+  const int y = t / C::TL, s = t % C::TL;
+  float2* row = P + y * C::RS;
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = row[ppad(s + C::TL * r)];
+  dft16(v, sg);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) row[ppad(s * 16 + r)] = v[r];
+  __syncthreads();
+  // butterfly (s, q) reads and writes only the positions jj + 16 r of the
+  // row, jj = s + TL q, and jj is unique to (s, q): in place, no barrier
+#pragma unroll
+  for (int q = 0; q < C::B2; ++q) {
+    const int jj = s + C::TL * q;
+    float2 u[C::R2];
+#pragma unroll
+    for (int r = 0; r < C::R2; ++r) u[r] = row[ppad(jj + 16 * r)];
+#pragma unroll
+    for (int r = 1; r < C::R2; ++r) u[r] = cmul(u[r], INV ? cconj(twl[jj * r]) : twl[jj * r]);
+    dft_r<C::R2>(u, sg);
+#pragma unroll
+    for (int p = 0; p < C::R2; ++p) row[ppad(jj + 16 * p)] = u[p];
+  }
+}
+
+// y lines: thread (column x, slot s).  mid() runs between the first stage's
+// write-back and its barrier; the second stage hands the outputs y = jj + 16 p
+// of butterfly (s, q) to sink(jj, x, u) (in place into LDS is safe: jj is
+// unique to (s, q)).
+template <int NP, bool INV, class Mid, class Sink>
+__device__ __forceinline__ void plane_cols(float2* P, const float2* twl, int t, Mid mid, Sink sink) {
+  using C = PlaneCfg<NP>;
+  constexpr float sg = INV ? 1.f : -1.f;
+  const int x = t % NP, s = t / NP;
+  float2* col = P + ppad(x);
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = col[(s + C::TL * r) * C::RS];
+  dft16(v, sg);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 16; ++r) col[(s * 16 + r) * C::RS] = v[r];
+  mid();
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < C::B2; ++q) {
+    const int jj = s + C::TL * q;
+    float2 u[C::R2];
+#pragma unroll
+    for (int r = 0; r < C::R2; ++r) u[r] = col[(jj + 16 * r) * C::RS];
+#pragma unroll
+    for (int r = 1; r < C::R2; ++r) u[r] = cmul(u[r], INV ? cconj(twl[jj * r]) : twl[jj * r]);
+    dft_r<C::R2>(u, sg);
+    sink(jj, x, u);
+  }
+}
+
+// The thread's 16 coalesced values (element e = t + T r of the plane) into LDS.
+template <int NP>
+__device__ __forceinline__ void plane_put(float2* P, int t, const float2 (&v)[16]) {
+  using C = PlaneCfg<NP>;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int e = t + C::T * r;
+    P[(e / NP) * C::RS + ppad(e % NP)] = v[r];
+  }
+}
+
 // Persistent over tasks (pair slot j, z plane): task = j * Nz + z, strided
 // by the grid; the loads of task + gridDim.x are issued before the current
-// plane's LDS stages and stores.
-template <int NP, int LM, int SM, int DT>
+// plane's LDS stages and stores.  INV: inverse DFT (+1 exponent).
+template <int NP, int LM, int SM, int DT, bool INV>
 __global__ __launch_bounds__(PlaneCfg<NP>::T) void k_plane(PassArgs a) {
   using C = PlaneCfg<NP>;
   extern __shared__ float2 P[];  // [NP][RS]
-  __shared__ float2 twl[NP];
+  __shared__ float2 twl[NP];     // exp(-2 pi i m / NP)
   const int t = threadIdx.x;
   const int ntask = a.Nz * a.nb;
-  for (int i = t; i < NP; i += C::T) {
-    float2 w = a.tw[i];
-    if (a.sgn > 0.f) w.y = -w.y;
-    twl[i] = w;
-  }
+  for (int i = t; i < NP; i += C::T) twl[i] = a.tw[i];
   // a pair of complex64 128^2 planes in flight (64 VGPRs) does not fit next
   // to the transform's registers: that pass loads its plane when it starts it
   constexpr bool kPrefetch = !(LM == LM_UIN && DT == OS3D_C64 && NP == 128);
@@ -180,70 +256,74 @@ __global__ __launch_bounds__(PlaneCfg<NP>::T) void k_plane(PassArgs a) {
     {
       float2 v[16];
       in.get(a, j, v);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int e = t + C::T * r;  // coalesced: element e of the plane
-        P[(e / NP) * C::RS + ppad(e % NP)] = v[r];
-      }
+      plane_put<NP>(P, t, v);
     }
     const int next = task + gridDim.x;
     if (kPrefetch && next < ntask) in.issue(a, next / a.Nz, (long long)(next % a.Nz) * NP * NP + t, C::T);
     __syncthreads();
-    // x lines: thread (row y, slot s)
-    {
-      const int y = t / C::TL, s = t % C::TL;
-      float2* row = P + y * C::RS;
-      float2 v[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = row[ppad(s + C::TL * r)];
-      dft16(v, a.sgn);
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < 16; ++r) row[ppad(s * 16 + r)] = v[r];
-      __syncthreads();
-      // butterfly (s, q) reads and writes only the positions jj + 16 r of
-      // the row, jj = s + TL q, and jj is unique to (s, q): in place, no barrier
-#pragma unroll
-      for (int q = 0; q < C::B2; ++q) {
-        const int jj = s + C::TL * q;
-        float2 u[C::R2];
-#pragma unroll
-        for (int r = 0; r < C::R2; ++r) u[r] = row[ppad(jj + 16 * r)];
-#pragma unroll
-        for (int r = 1; r < C::R2; ++r) u[r] = cmul(u[r], twl[jj * r]);
-        dft_r<C::R2>(u, a.sgn);
-#pragma unroll
-        for (int p = 0; p < C::R2; ++p) row[ppad(jj + 16 * p)] = u[p];
-      }
-    }
+    plane_rows<NP, INV>(P, twl, t);
     __syncthreads();
-    // y lines: thread (column x, slot s); the last stage stores to memory
-    {
-      const int x = t % NP, s = t / NP;
-      float2* col = P + ppad(x);
-      float2 v[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = col[(s + C::TL * r) * C::RS];
-      dft16(v, a.sgn);
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < 16; ++r) col[(s * 16 + r) * C::RS] = v[r];
-      if (kPrefetch && next < ntask) in.issue2(a, next / a.Nz, (long long)(next % a.Nz) * NP * NP + t, C::T);
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < C::B2; ++q) {
-        const int jj = s + C::TL * q;
-        float2 u[C::R2];
-#pragma unroll
-        for (int r = 0; r < C::R2; ++r) u[r] = col[(jj + 16 * r) * C::RS];
-#pragma unroll
-        for (int r = 1; r < C::R2; ++r) u[r] = cmul(u[r], twl[jj * r]);
-        dft_r<C::R2>(u, a.sgn);
-        float2 dummy[C::R2];
-        store_k<SM, DT, C::R2>(a, j, base + (long long)jj * NP + x, 16LL * NP, u, dummy);
-      }
-    }
+    plane_cols<NP, INV>(
+        P, twl, t,
+        [&]() {
+          if (kPrefetch && next < ntask) in.issue2(a, next / a.Nz, (long long)(next % a.Nz) * NP * NP + t, C::T);
+        },
+        [&](int jj, int x, const float2 (&u)[C::R2]) {
+          float2 dummy[C::R2];
+          store_k<SM, DT, C::R2>(a, j, base + (long long)jj * NP + x, 16LL * NP, u, dummy);
+        });
     __syncthreads();  // the plane buffer is rewritten by the next task
+  }
+}
+
+// Processing via scores on the plane path, both directions in one kernel:
+// the z-inverse-transformed plane of pair slot j (src) -> inverse plane DFT
+// -> Phi on the scores -> forward plane DFT -> back to the same place
+// (in place: a task owns its plane).  The scores never reach memory.
+template <int NP>
+__global__ __launch_bounds__(PlaneCfg<NP>::T) void k_plane_phi(PassArgs a) {
+  using C = PlaneCfg<NP>;
+  extern __shared__ float2 P[];
+  __shared__ float2 twl[NP];
+  const int t = threadIdx.x;
+  const int ntask = a.Nz * a.nb;
+  for (int i = t; i < NP; i += C::T) twl[i] = a.tw[i];
+  // the 128^2 variant needs its registers for Phi: it loads each plane when it starts it
+  constexpr bool kPrefetch = NP != 128;
+  PlaneIn<LM_C, OS3D_C64> in;
+  int task = blockIdx.x;
+  if (kPrefetch && task < ntask) in.issue(a, task / a.Nz, (long long)(task % a.Nz) * NP * NP + t, C::T);
+  for (; task < ntask; task += gridDim.x) {
+    const int j = task / a.Nz;
+    const long long base = (long long)(task % a.Nz) * NP * NP;
+    if (!kPrefetch) in.issue(a, j, base + t, C::T);
+    {
+      float2 v[16];
+      in.get(a, j, v);
+      plane_put<NP>(P, t, v);
+    }
+    const int next = task + gridDim.x;
+    if (kPrefetch && next < ntask) in.issue(a, next / a.Nz, (long long)(next % a.Nz) * NP * NP + t, C::T);
+    __syncthreads();
+    plane_rows<NP, true>(P, twl, t);
+    __syncthreads();
+    plane_cols<NP, true>(
+        P, twl, t, []() {},
+        [&](int jj, int x, const float2 (&u)[C::R2]) {
+#pragma unroll
+          for (int p = 0; p < C::R2; ++p) P[(jj + 16 * p) * C::RS + ppad(x)] = phi_apply(a, j, u[p]);
+        });
+    __syncthreads();
+    plane_rows<NP, false>(P, twl, t);
+    __syncthreads();
+    plane_cols<NP, false>(
+        P, twl, t, []() {},
+        [&](int jj, int x, const float2 (&u)[C::R2]) {
+          float2* d = a.dst_c + j * a.dst_stride + base + (long long)jj * NP + x;
+#pragma unroll
+          for (int p = 0; p < C::R2; ++p) d[(long long)p * 16 * NP] = u[p];
+        });
+    __syncthreads();
   }
 }
 
@@ -258,21 +338,34 @@ static int cu_count() {
   return n;
 }
 
+// Raises the dynamic-LDS limit of each plane kernel once.
+static void reserve_lds(const void* kernel, size_t lds) {
+  static std::mutex mu;
+  static std::unordered_set<const void*> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.insert(kernel).second)
+    (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <class K>
+static void launch_persistent(K kernel, int NP, long long ntask, size_t lds, int threads, const PassArgs& a,
+                              hipStream_t st) {
+  reserve_lds((const void*)kernel, lds);
+  // one workgroup per CU for 128^2 planes (LDS), four for 64^2; each loops over its tasks
+  const int per_cu = (NP == 128) ? 1 : 4;
+  const unsigned grid = (unsigned)std::min<long long>(ntask, (long long)cu_count() * per_cu);
+  hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, st, a);
+}
+
 template <int NP, int LM, int SM, int DT>
 static void launch_plane_np(const PassArgs& a, int grid_y, hipStream_t st) {
   using C = PlaneCfg<NP>;
   const size_t lds = (size_t)NP * C::RS * sizeof(float2);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_plane<NP, LM, SM, DT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    attr_set = true;
-  }
-  // one workgroup per CU for 128^2 planes (LDS), four for 64^2; each loops over its tasks
-  const int per_cu = (NP == 128) ? 1 : 4;
   const long long ntask = (long long)a.Nz * grid_y;
-  const unsigned grid = (unsigned)std::min<long long>(ntask, (long long)cu_count() * per_cu);
-  hipLaunchKernelGGL((k_plane<NP, LM, SM, DT>), dim3(grid), dim3(C::T), lds, st, a);
+  if (a.sgn > 0.f)
+    launch_persistent(k_plane<NP, LM, SM, DT, true>, NP, ntask, lds, C::T, a, st);
+  else
+    launch_persistent(k_plane<NP, LM, SM, DT, false>, NP, ntask, lds, C::T, a, st);
 }
 
 template <int LM, int SM, int DT>
@@ -294,11 +387,19 @@ void launch_plane(const PassArgs& a, int grid_y, hipStream_t st) {
   }
 }
 
+void launch_plane_phi(const PassArgs& a, int grid_y, hipStream_t st) {
+  const long long ntask = (long long)a.Nz * grid_y;
+  if (a.Nx == 128)
+    launch_persistent(k_plane_phi<128>, 128, ntask, (size_t)128 * PlaneCfg<128>::RS * sizeof(float2),
+                      PlaneCfg<128>::T, a, st);
+  else
+    launch_persistent(k_plane_phi<64>, 64, ntask, (size_t)64 * PlaneCfg<64>::RS * sizeof(float2),
+                      PlaneCfg<64>::T, a, st);
+}
+
 template void launch_plane<LM_REAL, SM_C>(const PassArgs&, int, hipStream_t);
 template void launch_plane<LM_C, SM_UOUT>(const PassArgs&, int, hipStream_t);
-template void launch_plane<LM_C, SM_PHI>(const PassArgs&, int, hipStream_t);
 template void launch_plane<LM_C, SM_REAL>(const PassArgs&, int, hipStream_t);
 template void launch_plane<LM_UIN, SM_C>(const PassArgs&, int, hipStream_t);
-template void launch_plane<LM_C, SM_C>(const PassArgs&, int, hipStream_t);
 
 }  // namespace os3d
