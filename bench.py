@@ -48,6 +48,7 @@ def parse():
                     help="reconstruct: forward + reconstruction (the metric); process: processing via scores "
                          "(Eq. 23, soft threshold p = 1.5) fused so that U never reaches memory")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stream-ceiling", action="store_true", help="skip the device copy/read/write rates")
     ap.add_argument("--cpu-orients", type=int, default=4, help="orientations in the oracle's timed sample")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests in the stream")
     ap.add_argument("--rate", type=float, default=50.0, help="serving: mean arrivals per second")
@@ -255,10 +256,40 @@ def main():
         "wall_s_timed": wall,
         "source_digest": digest,
     }
+    if not args.no_stream_ceiling:
+        out["stream_ceiling"] = stream_ceiling(dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_orients)
     print(json.dumps(out), flush=True)
+
+
+def stream_ceiling(dev, nbytes=2 << 30, reps=10):
+    """HBM rates a plain device copy, read (sum) and write (fill) reach on
+    this GPU with torch's own kernels over 2 GiB buffers: the practical
+    ceiling the kernels' rates compare with (the spec peak is 8 TB/s)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+
+    def rate(fn, moved):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return moved * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+
+    out = {"copy_GBs": rate(lambda: b.copy_(a), 2 * nbytes),
+           "read_GBs": rate(lambda: a.sum(), nbytes),
+           "write_GBs": rate(lambda: b.fill_(1.0), nbytes),
+           "buffer_bytes": nbytes}
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def serve_main(args, dev):

@@ -72,9 +72,12 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
   load_twiddles(a, twl);
   const long long base = (long long)tile << 14;
   float2 spec[16];
-  {
+  if constexpr (LM == LM_MULBANK) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) spec[r] = a.src_c[base + t + r * 1024];
+  } else {
     float unused = 0.f;
-    load_k<(LM == LM_MULBANK) ? LM_C : LM, OS3D_C64, 16>(a, 0, base + t, 1024, spec, unused);
+    load_k<LM, OS3D_C64, 16>(a, 0, base + t, 1024, spec, unused);
   }
   float pnx[16];
   if constexpr (LM == LM_MULBANK) {
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
     const float2* T = a.src_c + (long long)j * a.src_stride + (long long)tile * 16 * 1024;
     float2 v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = T[q * 1024 + t];
+    for (int q = 0; q < 16; ++q) v[q] = ldnt(T + q * 1024 + t);
     dft16(v, a.sgn);  // over n1 -> k1
     {
       const int g = t & 3, z = t >> 2;

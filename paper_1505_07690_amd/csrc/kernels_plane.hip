@@ -43,6 +43,7 @@ __device__ __forceinline__ int ppad(int x) { return x + (x >> 4); }
 // for these shapes) and the value index in a scalar offset, so the 16 or 32
 // loads in flight hold no per-load address registers.
 constexpr int kBufDword3 = 0x00020000;  // raw 32-bit records, no format conversion
+constexpr int kNT = 2;                  // cache policy: non-temporal (streamed once)
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t volume_rsrc(const void* base, long long bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufDword3);
@@ -59,7 +60,7 @@ struct PlaneIn<LM_C, DT> {
     const int vo = (int)(e0 * 8);
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-      r[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, i * T * 8, 0));
+      r[i] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, i * T * 8, kNT));
   }
   __device__ __forceinline__ void issue2(const PassArgs&, int, long long, int) {}
   __device__ __forceinline__ void get(const PassArgs&, int, float2 (&v)[16]) const {
@@ -76,7 +77,7 @@ struct PlaneIn<LM_REAL, DT> {
     const int vo = (int)(e0 * 4);
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-      r[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, i * T * 4, 0));
+      r[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, vo, i * T * 4, kNT));
   }
   __device__ __forceinline__ void issue2(const PassArgs&, int, long long, int) {}
   __device__ __forceinline__ void get(const PassArgs&, int, float2 (&v)[16]) const {
@@ -107,9 +108,9 @@ struct PlaneIn<LM_UIN, DT> {
   Word ra[16], rb[16];
   __device__ __forceinline__ static Word ld(__amdgpu_buffer_rsrc_t rs, int vo, int so) {
     if constexpr (DT == OS3D_C64)
-      return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
+      return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, kNT));
     else
-      return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0);
+      return __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, kNT);
   }
   // the two members of the pair are issued at two points of the previous
   // plane's work, which keeps the registers in flight within the budget
