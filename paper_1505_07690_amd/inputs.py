@@ -18,7 +18,8 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["tubes", "tubes_device", "icosahedral_orientations", "bandlimited", "CONFIGS", "config_volume",
+__all__ = ["tubes", "tubes_device", "icosahedral_orientations", "platonic_orientations", "bandlimited", "CONFIGS",
+           "config_volume",
            "serving_stream", "SERVING_SHAPES"]
 
 
@@ -170,6 +171,30 @@ def icosahedral_orientations(level):
             new_faces += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
         verts, faces = pts, new_faces
     return np.array(verts, dtype=np.float64)
+
+
+def platonic_orientations(name):
+    """Vertex directions of a platonic solid (Sec. 2.1 samples the sphere with
+    them): "tetrahedron" (4, not antipodally closed), "octahedron" (6),
+    "cube" (8), "dodecahedron" (20), "icosahedron" (12).  float64 [N][3]."""
+    p = (1.0 + 5.0 ** 0.5) / 2.0
+    if name == "tetrahedron":
+        v = [(1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)]
+    elif name == "octahedron":
+        v = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    elif name == "cube":
+        v = [(a, b, c) for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)]
+    elif name == "dodecahedron":
+        v = [(a, b, c) for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)]
+        for a in (-1, 1):
+            for b in (-1, 1):
+                v += [(0, a / p, b * p), (a / p, b * p, 0), (a * p, 0, b / p)]
+    elif name == "icosahedron":
+        return icosahedral_orientations(0)
+    else:
+        raise ValueError(name)
+    v = np.array(v, dtype=np.float64)
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
 
 
 def bandlimited(shape, frac, seed=0, batch=None, dtype=np.float32):

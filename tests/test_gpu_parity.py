@@ -76,6 +76,11 @@ CASES = {
     # whole-plane path: 128 x 128 planes over a z axis of 20 (radix 4 x 5 in the z pass)
     "plane128": lambda: ((20, 128, 128), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                          inputs.tubes((20, 128, 128), 3, 1.5, 0.1, 0, 15)),
+    # platonic sets: the tetrahedron has no antipodes (pair path off), the dodecahedron has
+    "tetra": lambda: ((12, 10, 16), inputs.platonic_orientations("tetrahedron"), _oracle_params(6, 4),
+                      inputs.tubes((12, 10, 16), 2, 1.2, 0.1, 0, 18)),
+    "dodeca": lambda: ((16, 12, 10), inputs.platonic_orientations("dodecahedron"), _oracle_params(10, 20),
+                       inputs.tubes((16, 12, 10), 2, 1.2, 0.1, 0, 19)),
     # small N with radix-2 only and a long axis
     "long4x6x64": lambda: ((4, 6, 64), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                            inputs.tubes((4, 6, 64), 2, 1.0, 0.1, 0, 8)),
@@ -100,7 +105,7 @@ def test_bank_and_M_parity(case):
     assert rel(psi, ob["psi_hat"]) < TOL
     assert rel(gb.M().cpu().numpy(), ob["M"]) < TOL
     assert abs(gb.kappa - ob["kappa"]) < 1e-6 * ob["kappa"]
-    assert gb.paired == (case["name"] != "unpaired_plate")
+    assert gb.paired == (case["name"] not in ("unpaired_plate", "tetra"))
 
 
 def test_forward_parity(case):

@@ -615,3 +615,17 @@ def test_empty_normalisation_band_is_an_error():
         O.build_bank((2, 3, 3), n, p)
     b = O.build_bank((2, 3, 4), n, p)
     assert np.isfinite(b["kappa"]) and b["kappa"] > 0
+
+
+def test_platonic_orientation_sets():
+    """Vertex counts, unit length, equal nearest-neighbour angles, and which
+    sets are antipodally closed (all but the tetrahedron)."""
+    for name, n in (("tetrahedron", 4), ("octahedron", 6), ("cube", 8), ("dodecahedron", 20), ("icosahedron", 12)):
+        v = inputs.platonic_orientations(name)
+        assert v.shape == (n, 3)
+        assert np.allclose(np.linalg.norm(v, axis=1), 1.0, atol=1e-15)
+        d = np.linalg.norm(v[:, None] - v[None], axis=2) + 10 * np.eye(n)
+        nn = d.min(axis=1)
+        assert np.allclose(nn, nn[0], atol=1e-12)
+        antip = np.linalg.norm(v[:, None] + v[None], axis=2).min(axis=1)
+        assert (np.max(antip) < 1e-12) == (name != "tetrahedron")
