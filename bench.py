@@ -32,6 +32,8 @@ WORKLOADS = {
     # name: (config key of the volume recipe, human label)
     "C": "256^3 crossing tubes (40 tubes, sigma U[1,4], noise 0.3, seed 2), N_o=162, L=24",
     "B": "128^3 crossing tubes (12 tubes, 5 forced crossings, noise 0.2, seed 1), N_o=42, L=16",
+    "D": "differentiation: batch of 8 crossing-tube 128^3 volumes (seeds 30-37), N_o=42, L=16; forward + adjoint "
+         "(the autograd backward) of the batch",
     "E": "serving: Poisson stream of forward+reconstruct jobs (50 req/s, seed 4), shapes 64^3, 96x80x64, 128^3, "
          "160x128x128, 256^3, N_o in {42, 162}, L in {16, 24}, 12 crossing tubes per volume",
 }
@@ -143,6 +145,9 @@ def main():
 
     if args.workload == "E":
         serve_main(args, dev)
+        return
+    if args.workload == "D":
+        grad_main(args, dev)
         return
 
     if args.copy_calibration:
@@ -261,6 +266,77 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_orients)
+    print(json.dumps(out), flush=True)
+
+
+def grad_main(args, dev):
+    """Differentiation workload: forward and adjoint (the hand-written
+    backward) of a batch of 8 volumes through the C ABI, then the whole
+    autograd step (loss = sum of w |U|^2 with a seeded mask) for context."""
+    import numpy as np
+    import torch
+
+    from paper_1505_07690_amd import inputs, os3d
+    from paper_1505_07690_amd.autograd import orientation_score
+
+    c = inputs.CONFIGS["B"]
+    shape, B = c["shape"], 8
+    orients = inputs.icosahedral_orientations(c["level"])
+    No, V = len(orients), int(np.prod(shape))
+    bank = os3d.Bank(shape, orients, os3d.make_params(L=c["L"], s_theta=inputs.s_theta_for(No)))
+    f = torch.from_numpy(np.stack([inputs.tubes(shape, c["tubes"], c["sigma"], c["noise"], c["pairs"], 30 + b)
+                                   for b in range(B)])).to(dev)
+    U = torch.empty((B, No) + shape, dtype=torch.complex64, device=dev)
+    g = torch.empty((B,) + shape, dtype=torch.float32, device=dev)
+    ws = bank.workspace()
+
+    def step():
+        os3d.forward(f, bank, ws=ws, out=U)
+        os3d.adjoint(U, bank, ws=ws, out=g)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for k in range(args.steps):
+        step()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+    ms = sum(per) / args.steps
+    # the autograd step: loss = sum w |U|^2 over (b, i, x), backward through the adjoint
+    w = torch.rand((B, No) + shape, generator=torch.Generator(device=dev).manual_seed(3), device=dev)
+    fr = f.clone().requires_grad_(True)
+
+    def auto_step():
+        Ua = orientation_score(fr, bank)
+        loss = torch.sum(w * (Ua.real ** 2 + Ua.imag ** 2))
+        fr.grad = None
+        loss.backward()
+
+    auto_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        auto_step()
+    torch.cuda.synchronize()
+    auto_ms = (time.perf_counter() - t0) / 3 * 1e3
+    step_bytes = B * (V * No * 2 * 8 + 8 * V)
+    out = {
+        "metric": "voxel-orientations/sec forward+reconstruct, %HBM roofline; p50/p99 latency",
+        "value": B * V * No / (ms / 1e3),
+        "unit": "voxel-orientations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "p50_ms": float(np.percentile(per, 50)), "p99_ms": float(np.percentile(per, 99)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["D"], "shape": list(shape), "batch": B, "n_orients": No, "L": c["L"],
+                   "op": "forward + adjoint"},
+        "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBs": step_bytes / (ms / 1e3) / 1e9,
+                          "frac": step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "autograd_step_ms": auto_ms,
+        "roofline": None,
+    }
     print(json.dumps(out), flush=True)
 
 
