@@ -5,13 +5,16 @@
 //     h[k, i] = sum_{(l,m)} Y_lm(w_hat_k) S[(l,m), i]
 // (S: steering matrix a_l sqrt(4 pi/(2l+1)) Y_lm(n_i), the addition-theorem
 // form of the Wigner-D rotation of Eqs. 17-19).  Each workgroup owns 256
-// frequency points: every thread generates its point's real spherical
-// harmonics for one order m at a time with the FP64 normalised associated
-// Legendre recursion, rounds them to FP32 into LDS, and the four waves run
-// v_mfma_f32_16x16x4_f32 over that K-chunk against S streamed from L2.  The
-// epilogue multiplies by the FP64 radial window g(rho) (Eq. 10), applies the
-// Nyquist and DC rules, writes the bank rows and accumulates
-// sum_i psi_i^2 (Eq. 9) in FP64 with a fixed-order cross-lane tree.
+// frequency points: every thread generates its point's associated Legendre
+// values Q_l^m for one order m at a time with the FP64 normalised recursion
+// and rounds them to FP32 into LDS; the real harmonics of that order are
+// Q_l^m times the real and imaginary parts of (x + iy)^m, applied in
+// registers to the MFMA A operand.  The four waves run
+// v_mfma_f32_16x16x4_f32 over the chunk against the chunk's rows of S
+// (prefetched during the recursion and staged in LDS).  The epilogue
+// multiplies by the FP64 radial window g(rho) (Eq. 10), applies the Nyquist
+// and DC rules, writes the bank rows and accumulates sum_i psi_i^2 (Eq. 9)
+// in FP64 with a fixed-order cross-lane tree.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -28,7 +31,7 @@ constexpr int kBankPts = 256;   // frequency points per workgroup
 constexpr int kYStride = 272;   // LDS row stride (floats) of the K-chunk buffer
 constexpr int kColBlocks = 3;                  // 16-column MFMA blocks per sweep
 constexpr int kColsPerSweep = 16 * kColBlocks;
-constexpr int kStageRegs = 12;                 // steering values prefetched per thread and chunk
+constexpr int kStageRegs = 11;                 // steering values prefetched per thread and chunk
 
 struct BankArgs {
   int layout;  // storage order of the frequency points (natural or four-step tiles)
@@ -63,10 +66,17 @@ __device__ inline double radial_g(double rho2, double t_inv, int N) {
   return acc;
 }
 
-__global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
-  extern __shared__ float Ybuf[];  // [kchunk_max][kYStride], then [kchunk_max][kColsPerSweep]
+// One K-chunk per m: the rows Q_l^m (l = m..L, times sqrt 2 for m > 0) of
+// the 256 points are generated once into LDS; the cos rows of the chunk are
+// Q cos(m phi) and the sin rows Q sin(m phi), so the A operand of either half
+// is the same LDS value times the point's (x + iy)^m real or imaginary part,
+// applied in registers.  Half the LDS of storing both halves: three
+// workgroups per CU.
+__global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
+  extern __shared__ float Ybuf[];  // [qpad_max][kYStride], then cos and sin steering rows [2][qpad_max][cols]
   __shared__ double gsh[kBankPts];
   __shared__ double Msh[kBankPts];
+  __shared__ float crsh[kBankPts], cish[kBankPts];
   __shared__ int dcsh[kBankPts];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -78,8 +88,7 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
   const double* alm = a.tab + nn;
   const double* blm = a.tab + nn + nn * nn;
   const int* koff = a.koff;
-  const int* kpad = a.koff + nn;
-  float* Sbuf = Ybuf + a.maxpad * kYStride;  // this sweep's steering columns of chunk m
+  float* Scos = Ybuf + a.maxpad * kYStride;
 
   // this thread's frequency point
   double ux = 0.0, uy = 0.0, uz = 1.0, g = 0.0;
@@ -117,25 +126,27 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
         cr = nr;
         ci = ni;
       }
-      const int len = (m == 0) ? nn : 2 * (nn - m);
-      const int pad = kpad[m];
-      // issue the loads of the chunk's steering rows (this sweep's columns)
-      // first, branch-free, so that they complete during the recursion
+      const int nq = nn - m;            // rows l = m..L
+      const int qpad = (nq + 3) & ~3;
+      // issue the loads of the chunk's cos and sin steering rows (this
+      // sweep's columns) first, branch-free, so that they complete during
+      // the recursion
       const float* Sm = a.S + (long long)koff[m] * a.Npad;
-      const int stotal = pad * kColsPerSweep;
+      const int half = qpad * kColsPerSweep;
       float sv[kStageRegs];
 #pragma unroll
       for (int u = 0; u < kStageRegs; ++u) {
         const int idx = u * kBankPts + tid;
-        const int kr = idx / kColsPerSweep, cc = idx - kr * kColsPerSweep;
-        const bool ok = idx < stotal && c0 + cc < a.Npad;
-        const float v = Sm[ok ? (long long)kr * a.Npad + c0 + cc : 0];
+        const int part = idx >= half, id2 = idx - part * half;
+        const int kr = id2 / kColsPerSweep, cc = id2 - kr * kColsPerSweep;
+        const bool ok = idx < 2 * half && kr < nq && c0 + cc < a.Npad && (m > 0 || part == 0);
+        const float v = Sm[ok ? (long long)(kr + part * nq) * a.Npad + c0 + cc : 0];
         sv[u] = ok ? v : 0.f;
       }
-      // generate chunk m: Q_l^m for l = m..L (sinus power factored out)
+      // Q_l^m for l = m..L (sinus power factored out), FP64 recursion
       {
         double q2 = 0.0, q1 = qmm[m];
-        const double s2 = 1.4142135623730950488;
+        const double sc = (m == 0) ? 1.0 : 1.4142135623730950488;
         for (int l = m; l <= L; ++l) {
           double q;
           if (l == m)
@@ -146,37 +157,53 @@ __global__ __launch_bounds__(256) void k_bank_synth(BankArgs a) {
             q = alm[l * nn + m] * (uz * q1 - blm[l * nn + m] * q2);
           if (l > m) q2 = q1;
           q1 = q;
-          if (m == 0) {
-            Ybuf[(l)*kYStride + tid] = (float)q;
-          } else {
-            Ybuf[(l - m) * kYStride + tid] = (float)(s2 * q * cr);
-            Ybuf[(nn - m + l - m) * kYStride + tid] = (float)(s2 * q * ci);
-          }
+          Ybuf[(l - m) * kYStride + tid] = (float)(sc * q);
         }
-        for (int kk = len; kk < pad; ++kk) Ybuf[kk * kYStride + tid] = 0.f;
+        for (int kk = nq; kk < qpad; ++kk) Ybuf[kk * kYStride + tid] = 0.f;
+        crsh[tid] = (float)cr;
+        cish[tid] = (float)ci;
       }
-      // stage the steering rows in LDS (rows past kStageRegs * 256 values,
-      // needed only for L > 31, are loaded here)
+      // stage the steering rows in LDS (values past kStageRegs * 256, needed
+      // only for L > 31, are loaded here)
 #pragma unroll
       for (int u = 0; u < kStageRegs; ++u)
-        if (u * kBankPts + tid < stotal) Sbuf[u * kBankPts + tid] = sv[u];
-      for (int idx = kStageRegs * kBankPts + tid; idx < stotal; idx += kBankPts) {
-        const int kr = idx / kColsPerSweep, cc = idx - kr * kColsPerSweep;
-        Sbuf[idx] = (c0 + cc < a.Npad) ? Sm[(long long)kr * a.Npad + c0 + cc] : 0.f;
+        if (u * kBankPts + tid < 2 * half) Scos[u * kBankPts + tid] = sv[u];
+      for (int idx = kStageRegs * kBankPts + tid; idx < 2 * half; idx += kBankPts) {
+        const int part = idx >= half, id2 = idx - part * half;
+        const int kr = id2 / kColsPerSweep, cc = id2 - kr * kColsPerSweep;
+        const bool ok = kr < nq && c0 + cc < a.Npad && (m > 0 || part == 0);
+        Scos[idx] = ok ? Sm[(long long)(kr + part * nq) * a.Npad + c0 + cc] : 0.f;
       }
       __syncthreads();
-      for (int k0 = 0; k0 < pad; k0 += 4) {
+      float crv[4], civ[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        crv[r] = crsh[wave * 64 + r * 16 + (lane & 15)];
+        civ[r] = cish[wave * 64 + r * 16 + (lane & 15)];
+      }
+      const float* Sc = Scos;
+      const float* Ss = Scos + half;  // the sin rows follow the cos rows
+      for (int k0 = 0; k0 < qpad; k0 += 4) {
         const int kr = k0 + (lane >> 4);
-        float af[4], bf[kColBlocks];
+        float q[4], bc[kColBlocks], bs[kColBlocks];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) af[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
+        for (int r = 0; r < 4; ++r) q[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
 #pragma unroll
-        for (int c = 0; c < kColBlocks; ++c) bf[c] = Sbuf[kr * kColsPerSweep + c * 16 + (lane & 15)];
-        // all column blocks, also past Npad (zero columns): no branch between the MFMAs
+        for (int c = 0; c < kColBlocks; ++c) {
+          bc[c] = Sc[kr * kColsPerSweep + c * 16 + (lane & 15)];
+          bs[c] = Ss[kr * kColsPerSweep + c * 16 + (lane & 15)];
+        }
+        // all column blocks, also past Npad (zero columns); for m = 0 the sin
+        // rows are zero: no branch between the MFMAs
 #pragma unroll
-        for (int c = 0; c < kColBlocks; ++c)
+        for (int r = 0; r < 4; ++r) {
+          const float ac = q[r] * crv[r], as = q[r] * civ[r];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[r], bf[c], acc[r][c], 0, 0, 0);
+          for (int c = 0; c < kColBlocks; ++c) {
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac, bc[c], acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bs[c], acc[r][c], 0, 0, 0);
+          }
+        }
       }
       __syncthreads();
     }
@@ -423,12 +450,10 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   a.psi = b->d.psi;
   a.Mh = b->d.Mh;
   a.dc_value = b->dc_value;
-  int maxpad = 0;
-  using std::max;
-  KLayout kl = k_layout(L);
-  for (int m = 0; m <= L; ++m) maxpad = max(maxpad, kl.pad[m]);
+  // LDS rows per chunk: the L + 1 - m values Q_l^m, padded to 4 (largest at m = 0)
+  const int maxpad = (nn + 3) / 4 * 4;
   a.maxpad = maxpad;
-  size_t lds = (size_t)maxpad * (kYStride + kColsPerSweep) * sizeof(float);
+  size_t lds = (size_t)maxpad * (kYStride + 2 * kColsPerSweep) * sizeof(float);
   const long long nblk = (b->V + kBankPts - 1) / kBankPts;
   if (hipFuncSetAttribute((const void*)k_bank_synth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
       hipSuccess) {
