@@ -51,7 +51,9 @@ def parse():
                          "(Eq. 23, soft threshold p = 1.5) fused so that U never reaches memory")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream-ceiling", action="store_true", help="skip the device copy/read/write rates")
-    ap.add_argument("--cpu-orients", type=int, default=4, help="orientations in the oracle's timed sample")
+    ap.add_argument("--cpu-orients", type=int, default=None,
+                    help="orientations in the oracle's timed sample (default: 12 of 162 at 256^3, all 42 at 128^3, "
+                         "about 10 s of host work each)")
     ap.add_argument("--requests", type=int, default=1000, help="serving: requests in the stream")
     ap.add_argument("--rate", type=float, default=50.0, help="serving: mean arrivals per second")
     ap.add_argument("--hbm-budget-gb", type=float, default=160.0, help="serving: HBM budget of the server")
@@ -265,7 +267,8 @@ def main():
         out["stream_ceiling"] = stream_ceiling(dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_orients)
+        n_sample = args.cpu_orients or {"C": 12, "B": 42}[args.workload]
+        out["cpu_baseline"] = cpu_baseline(args.workload, n_sample)
     print(json.dumps(out), flush=True)
 
 

@@ -152,8 +152,11 @@ os3d_status os3d_bank_psi(const os3d_bank* bank, int32_t i, float* psi_dev, void
 /* Writes M (float32 [Nz][Ny][Nx], natural DFT index order) into M_dev (device). */
 os3d_status os3d_bank_M(const os3d_bank* bank, float* M_dev, void* stream);
 
-/* Bytes of workspace that os3d_forward / os3d_adjoint / os3d_reconstruct
- * need for this bank (independent of the batch size and score dtype). */
+/* Bytes of workspace that os3d_forward / os3d_adjoint / os3d_reconstruct /
+ * os3d_process need for this bank (independent of the batch size and score
+ * dtype).  A call uses the workspace until its work on `stream` has
+ * finished: calls that may overlap (different streams) need workspaces of
+ * their own; the bank itself is read-only and may be shared. */
 os3d_status os3d_workspace_bytes(const os3d_bank* bank, size_t* bytes);
 
 /* Discrete orientation score, Eq. (7): U[b][i] = IDFT(psi_hat_i DFT(f[b])),

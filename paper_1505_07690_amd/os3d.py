@@ -182,6 +182,9 @@ class Bank:
         return self.shape[0] * self.shape[1] * self.shape[2]
 
     def workspace(self):
+        """The bank's own workspace (the default of the compute calls).  Calls
+        that run concurrently on different streams must pass workspaces of
+        their own (`ws=`); the bank itself may be shared."""
         import torch
         if self._ws is None:
             self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
