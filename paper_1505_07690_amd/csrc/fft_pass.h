@@ -151,12 +151,15 @@ __device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long 
 // Phi of processing via scores applied to one transformed value v (times
 // out_scale = 1/V), times 2 for a stored antipodal pair: for real f the pair
 // contributes Phi(U_n) + conj(Phi(U_-n)) = 2 Phi(U_n) to the reconstruction.
+// |U|^(p-1) = 2^((p-1)/2 log2 |U|^2) with the hardware base-2 logarithm
+// and exponential (about 1 ulp each; powf costs ~170 instructions).
 __device__ __forceinline__ float2 phi_apply(const PassArgs& a, int j, float2 v) {
   const float2 u = cscale(v, a.out_scale);
   const float mult = (a.ob[j] >= 0) ? 2.f : 1.f;
   if (a.phi_kind == 1) {
-    const float m = sqrtf(u.x * u.x + u.y * u.y);
-    return cscale(u, (m > 0.f) ? mult * powf(m, a.phi_p - 1.f) : 0.f);
+    const float m2 = u.x * u.x + u.y * u.y;
+    const float f = __builtin_amdgcn_exp2f(0.5f * (a.phi_p - 1.f) * __builtin_amdgcn_logf(m2));
+    return cscale(u, (m2 > 0.f) ? mult * f : 0.f);
   }
   return cscale(u, mult);
 }
