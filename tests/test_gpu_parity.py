@@ -81,6 +81,11 @@ CASES = {
                       inputs.tubes((12, 10, 16), 2, 1.2, 0.1, 0, 18)),
     "dodeca": lambda: ((16, 12, 10), inputs.platonic_orientations("dodecahedron"), _oracle_params(10, 20),
                        inputs.tubes((16, 12, 10), 2, 1.2, 0.1, 0, 19)),
+    # degenerate banks: L = 0 (every profile isotropic) and a single orientation
+    "L0": lambda: ((10, 12, 8), inputs.icosahedral_orientations(0), _oracle_params(0, 12),
+                   inputs.tubes((10, 12, 8), 2, 1.2, 0.1, 0, 20)),
+    "single": lambda: ((12, 8, 10), np.array([[0.0, 0.0, 1.0]]), _oracle_params(8, 12),
+                       inputs.tubes((12, 8, 10), 2, 1.2, 0.1, 0, 21)),
     # small N with radix-2 only and a long axis
     "long4x6x64": lambda: ((4, 6, 64), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                            inputs.tubes((4, 6, 64), 2, 1.0, 0.1, 0, 8)),
@@ -105,7 +110,7 @@ def test_bank_and_M_parity(case):
     assert rel(psi, ob["psi_hat"]) < TOL
     assert rel(gb.M().cpu().numpy(), ob["M"]) < TOL
     assert abs(gb.kappa - ob["kappa"]) < 1e-6 * ob["kappa"]
-    assert gb.paired == (case["name"] not in ("unpaired_plate", "tetra"))
+    assert gb.paired == (case["name"] not in ("unpaired_plate", "tetra", "single"))
 
 
 def test_forward_parity(case):
