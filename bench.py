@@ -138,7 +138,6 @@ def main():
     import numpy as np
     import torch
 
-    import oracle as O
     from paper_1505_07690_amd import inputs, os3d
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -167,7 +166,7 @@ def main():
     orients = inputs.icosahedral_orientations(c["level"])
     No = len(orients)
     V = int(np.prod(shape))
-    p = O.WaveletParams(L=c["L"], s_theta=inputs.s_theta_for(No))
+    p = os3d.make_params(L=c["L"], s_theta=inputs.s_theta_for(No))
     vol = inputs.config_volume(args.workload)
     print(f"[bench] workload {args.workload}: {WORKLOADS[args.workload]}; dtype {args.dtype}", file=sys.stderr,
           flush=True)
