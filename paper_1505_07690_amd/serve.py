@@ -213,6 +213,12 @@ class Server:
                        vo_per_s=sum(r.vo for r in ok) / max(t1 - t0, 1e-9),
                        max_batch=max(r.batch for r in ok),
                        mean_batch=float(np.mean([r.batch for r in ok])))
+            per = collections.defaultdict(list)
+            for r in ok:
+                per[r.key].append((r.t_done - r.t_submit) * 1e3)
+            out["per_key"] = {"x".join(map(str, k[0])) + f" No={k[1]} L={k[2]}":
+                              dict(jobs=len(v), p50_ms=float(np.percentile(v, 50)), p99_ms=float(np.percentile(v, 99)))
+                              for k, v in sorted(per.items())}
         return out
 
     # --------------------------------------------------------- scheduler --
