@@ -258,6 +258,27 @@ def test_process_parity(case, phi, power):
     assert rel(got, want) < TOL
 
 
+def test_projection_parity(case):
+    """The projection W W^+ onto the orientation scores (Corollary of
+    Appendix A), composed from the reconstruction and the forward transform,
+    and its square, against the oracle with the same eps."""
+    from paper_1505_07690_amd import os3d
+    import torch
+    if np.prod(case["shape"]) > 1 << 20:
+        pytest.skip("four oracle transforms of every orientation take minutes at this size")
+    rng = np.random.default_rng(3)
+    No = len(case["orients"])
+    Un = (rng.standard_normal((No,) + case["shape"]) + 1j * rng.standard_normal((No,) + case["shape"]))
+    Un = Un.astype(np.complex64)
+    P1, _ = os3d.forward(os3d.reconstruct(torch.from_numpy(Un).cuda(), case["gb"]), case["gb"])
+    P2, _ = os3d.forward(os3d.reconstruct(P1, case["gb"]), case["gb"])
+    ob = case["ob"]
+    W1 = O.forward(O.reconstruct(Un.astype(np.complex128), ob), ob)
+    W2 = O.forward(O.reconstruct(W1, ob), ob)
+    assert rel(P1.cpu().numpy(), W1) < TOL
+    assert rel(P2.cpu().numpy(), W2) < TOL
+
+
 def test_three_pass_path_on_plane_shapes(torch_dev, monkeypatch):
     """Shapes with 64^2 or 128^2 planes take the z-line + whole-plane path;
     the three-pass path (forced for this bank) gives the same transform."""

@@ -421,6 +421,41 @@ def test_norm_and_theorem1():
     assert abs(ip.real - np.sum(f * g)) < 1e-12 * np.sqrt(np.sum(f * f) * np.sum(g * g))
 
 
+def test_projection_onto_score_space():
+    """Corollary of Appendix A: P = W W^+ projects the embedding space onto the
+    orientation scores.  With eps -> 0 (M > 0 off the zeroed Nyquist planes)
+    P is idempotent, self-adjoint in the M inner product, fixes every W f and
+    leaves a residual orthogonal to the scores.  W^+ returns a real volume, so
+    P is real-linear and the inner products are their real parts."""
+    shape = (8, 10, 6)
+    b, n, _ = _setup(shape, level=1, L=16)
+    rng = np.random.default_rng(31)
+
+    def cplx():
+        return rng.standard_normal((len(n),) + shape) + 1j * rng.standard_normal((len(n),) + shape)
+
+    def P(U):
+        return O.forward(O.reconstruct(U, b, eps=1e-300), b)
+
+    pos = b["M"] > 0
+    w = np.where(pos, 1.0 / np.where(pos, b["M"], 1.0), 0.0)
+
+    def ip_M(X, Y):
+        return sum(np.vdot(O.dft3(X[i]) * w, O.dft3(Y[i])) for i in range(X.shape[0])).real
+
+    U, V = cplx(), cplx()
+    PU = P(U)
+    assert rel(P(PU), PU) < 1e-9
+    a, c = ip_M(PU, V), ip_M(U, P(V))
+    assert abs(a - c) < 1e-12 * abs(a)
+    Wf = O.forward(rng.standard_normal(shape), b)
+    assert rel(P(Wf), Wf) < 1e-13
+    r = U - PU
+    assert abs(ip_M(r, Wf)) < 1e-10 * np.sqrt(ip_M(r, r) * ip_M(Wf, Wf))
+    # a random complex field is not a score: P removes a large part of it
+    assert rel(PU, U) > 0.5
+
+
 def test_adjoint_identity():
     b, n, _ = _setup((8, 6, 10))
     rng = np.random.default_rng(12)
