@@ -66,8 +66,12 @@ def parse():
 
 
 def kernel_source_digest():
+    """Digest of the sources the kernels are compiled from (the .hip files and
+    the headers they include; the host-only .cpp files are left out)."""
     h = hashlib.sha256()
     for fn in sorted(os.listdir(os.path.join(ROOT, "paper_1505_07690_amd", "csrc"))):
+        if not fn.endswith((".hip", ".h")):
+            continue
         with open(os.path.join(ROOT, "paper_1505_07690_amd", "csrc", fn), "rb") as f:
             h.update(fn.encode())
             h.update(f.read())

@@ -11,7 +11,8 @@
  * ---------------------------------------
  * - A volume is float32 [Nz][Ny][Nx] with x fastest (dims[] = {Nz, Ny, Nx}).
  *   Every dim must be >= 2 and have no prime factor other than 2, 3 and 5
- *   (others: OS3D_EUNSUPPORTED); the largest supported dim is 4096.
+ *   (others: OS3D_EUNSUPPORTED); the largest supported dim is 4096 and the largest
+ *   volume 2^31 voxels (larger: OS3D_EUNSUPPORTED).
  * - Orientations are float64 host arrays [N_o][3] of (x, y, z) unit vectors,
  *   in the caller's order (the set V of Sec. 2.1).  Scores keep that order.
  * - The DFT is unnormalised, F[k] = sum_x f[x] exp(-2 pi i k.x / N); its
@@ -43,7 +44,7 @@ typedef enum {
   OS3D_OK = 0,
   OS3D_EINVAL = -1,        /* invalid argument (null pointer, bad size, non-unit orientation, ...) */
   OS3D_ENOMEM = -2,        /* a caller-provided buffer is smaller than required */
-  OS3D_EUNSUPPORTED = -3,  /* a dim with a prime factor other than 2, 3, 5, or above 4096 */
+  OS3D_EUNSUPPORTED = -3,  /* a dim with a prime factor other than 2, 3, 5, above 4096, or V > 2^31 */
   OS3D_EDEVICE = -4        /* a HIP runtime call or kernel launch failed */
 } os3d_status;
 

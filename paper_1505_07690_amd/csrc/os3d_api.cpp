@@ -25,6 +25,9 @@ static int fail(int code, const std::string& msg) {
 
 static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// element-wise kernels launch one work-item per voxel: keep V within 2^31
+static constexpr long long kMaxVoxels = 1LL << 31;
+
 static int check_params(const os3d_wavelet_params* p) {
   if (!p) return fail(OS3D_EINVAL, "params is NULL");
   if (p->L < 0 || p->L > kMaxL) return fail(OS3D_EINVAL, "L must be in [0, 64]");
@@ -46,6 +49,8 @@ static int check_dims(const int64_t* dims) {
     if (dims[d] > kMaxDim || !factor235(dims[d]))
       return fail(OS3D_EUNSUPPORTED, "dims must be <= 4096 with prime factors 2, 3, 5 only");
   }
+  if (dims[0] * dims[1] * dims[2] > kMaxVoxels)
+    return fail(OS3D_EUNSUPPORTED, "the volume must hold at most 2^31 voxels");
   return OS3D_OK;
 }
 

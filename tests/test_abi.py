@@ -94,6 +94,12 @@ def test_errors_are_status_codes():
     assert nbytes.value > 12 // 2 * 512 * 4
     bad_dims = (ctypes.c_int64 * 3)(8, 7, 8)
     assert L.os3d_bank_bytes(bad_dims, n.ctypes.data, 12, ctypes.byref(good), ctypes.byref(nbytes)) == -3
+    huge = (ctypes.c_int64 * 3)(1024, 2048, 2048)  # every dim allowed, 2^32 voxels in all
+    assert L.os3d_bank_bytes(huge, n.ctypes.data, 12, ctypes.byref(good), ctypes.byref(nbytes)) == -3
+    assert b"2^31" in L.os3d_last_error()
+    largest = (ctypes.c_int64 * 3)(512, 2048, 2048)
+    assert L.os3d_bank_bytes(largest, n.ctypes.data, 12, ctypes.byref(good), ctypes.byref(nbytes)) == 0
+    assert nbytes.value > 6 * (1 << 31) * 4
     tiny = (ctypes.c_int64 * 3)(8, 1, 8)
     assert L.os3d_bank_bytes(tiny, n.ctypes.data, 12, ctypes.byref(good), ctypes.byref(nbytes)) == -1
     for field, val in [("L", -1), ("L", 65), ("s_theta", 0.0), ("k", -1), ("taylor_N", -2), ("gamma", 1.0),
@@ -131,10 +137,12 @@ def test_bank_bytes_halved_for_antipodal_sets():
     """Antipodally closed sets store one bank row per pair."""
     p = os3d.make_params(L=8, s_theta=1.3)
     n = inputs.icosahedral_orientations(0)
-    full = os3d.bank_bytes((16, 16, 16), n, p)
-    one_each = os3d.bank_bytes((16, 16, 16), n[:6] if False else np.vstack([n[:5], n[5:6]]), p)
     V = 16 ** 3
-    # 12 orientations in 6 pairs: 6 rows; the 6 unpaired vectors: 6 rows as well
-    assert abs(full - one_each) < 4096
-    half = os3d.bank_bytes((16, 16, 16), np.vstack([n, n[:1] * 0 + np.array([[0.0, 0.0, 1.0]])]), p)
-    assert half - full >= 6 * V * 4  # a 13th, unpaired orientation disables pairing: 13 rows
+    full = os3d.bank_bytes((16, 16, 16), n, p)
+    # six random directions have no antipodes: one row each, as many rows as the 6 pairs
+    v = np.random.default_rng(0).standard_normal((6, 3))
+    six = os3d.bank_bytes((16, 16, 16), v / np.linalg.norm(v, axis=1, keepdims=True), p)
+    assert six == full
+    # a 13th, unpaired orientation disables pairing: 13 rows
+    odd = os3d.bank_bytes((16, 16, 16), np.vstack([n, [[0.0, 0.0, 1.0]]]), p)
+    assert odd - full >= 7 * V * 4
