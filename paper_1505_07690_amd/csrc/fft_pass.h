@@ -130,7 +130,7 @@ __device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long 
   } else if constexpr (LM == LM_MULBANK) {
     const float p = a.psi[(long long)a.rows[j] * a.V + g];
     const float2 v = cscale(a.src_c[g], p);
-    asum += sqrtf(v.x * v.x + v.y * v.y);
+    if (a.partial) asum += sqrtf(v.x * v.x + v.y * v.y);  // scale bound of 16-bit storage only
     return v;
   } else if constexpr (LM == LM_UIN) {
     const int ia = a.oa[j], ib = a.ob[j];
@@ -214,9 +214,10 @@ __device__ __forceinline__ void load_k(const PassArgs& a, int j, long long g0, l
 #pragma unroll
     for (int r = 0; r < K; ++r) v[r] = a.src_c[g0 + r * d];
 #pragma unroll
-    for (int r = 0; r < K; ++r) {
-      v[r] = cscale(v[r], ps[r]);
-      asum += sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
+    for (int r = 0; r < K; ++r) v[r] = cscale(v[r], ps[r]);
+    if (a.partial) {  // scale bound of 16-bit storage only
+#pragma unroll
+      for (int r = 0; r < K; ++r) asum += sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
     }
   } else if constexpr (LM == LM_UIN) {
     const int ia = a.oa[j], ib = a.ob[j];

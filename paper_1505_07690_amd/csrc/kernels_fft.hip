@@ -491,6 +491,8 @@ static int pair_batch(const os3d_bank* b) {
   int nb = kMaxBatch;
   if (const char* e = getenv("OS3D_PAIR_BATCH")) nb = atoi(e);
   nb = std::max(1, std::min(std::min(nb, kMaxBatch), b->n_unique));
+  // one complex intermediate volume per pair of a launch: at most 8 GiB of them
+  nb = (int)std::max(1LL, std::min((long long)nb, (8LL << 30) / (b->V * (long long)sizeof(float2))));
   // the same number of pairs in every launch (no short last launch)
   const int launches = (b->n_unique + nb - 1) / nb;
   return (b->n_unique + launches - 1) / launches;

@@ -89,18 +89,17 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
   for (int j = 0; j < a.nb; ++j) {
     float2 v[16];
     if constexpr (LM == LM_MULBANK) {
-      float asum = 0.f;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        v[r] = cscale(spec[r], pnx[r]);
-        asum += sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
-      }
+      for (int r = 0; r < 16; ++r) v[r] = cscale(spec[r], pnx[r]);
       if (j + 1 < a.nb) {
         const float* prow = a.psi + (long long)a.rows[j + 1] * a.V + base + t;
 #pragma unroll
         for (int r = 0; r < 16; ++r) pnx[r] = prow[r * 1024];
       }
-      if (a.partial) {
+      if (a.partial) {  // scale bound of 16-bit storage only
+        float asum = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) asum += sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
         const float tot = block_sum_1024(asum, red);
         if (t == 0) a.partial[(long long)j * gridDim.x + blockIdx.x] = tot;
       }

@@ -210,3 +210,52 @@ def test_headline_process_properties(torch, headline):
     gm = os3d.process(-f, gb, "soft_threshold", 1.5).double()
     assert (torch.linalg.norm(g4 - 8.0 * g) / torch.linalg.norm(8.0 * g)).item() < TOL
     assert torch.equal(gm, -g)
+
+
+def test_largest_volume_gram_and_norm_identities(torch):
+    """The largest volume the library accepts, 2^31 voxels (2048 x 1024 x
+    1024, the three-pass path), with one antipodal pair: every index past
+    2^31 floats must be 64-bit.  No oracle at this size; instead the
+    properties that hold at any size (Theorem 1 and the Gram identity
+    W^H W = M behind Eq. 5): sum_i ||U_i||^2 = (1/V) sum_k M |F|^2 and
+    adjoint(forward(f)) = Re IDFT(M F), with F from torch's FFT in slabs."""
+    from paper_1505_07690_amd import os3d
+    shape = (2048, 1024, 1024)
+    V = 2048 * 1024 * 1024
+    n = np.array([[0.0, 0.6, 0.8], [0.0, -0.6, -0.8]])
+    bank = os3d.Bank(shape, n, os3d.make_params(L=8, s_theta=0.7))
+    assert bank.paired
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    f = torch.randn(shape, generator=g, device="cuda", dtype=torch.float32)
+    ws = torch.empty(bank.ws_bytes, dtype=torch.uint8, device="cuda")  # freed below, unlike the bank's own
+    U, _ = os3d.forward(f, bank, ws=ws)
+    assert torch.equal(U[1, -8:], torch.conj(U[0, -8:]).resolve_conj())
+    lhs = 0.0
+    for i in range(2):
+        for z0 in range(0, 2048, 128):
+            lhs += torch.sum(torch.view_as_real(U[i, z0:z0 + 128]).double() ** 2).item()
+    adj = os3d.adjoint(U, bank, ws=ws)
+    del U, ws
+    torch.cuda.empty_cache()
+    F = torch.empty(shape, dtype=torch.complex64, device="cuda")
+    for z0 in range(0, 2048, 128):
+        F[z0:z0 + 128] = torch.fft.fft2(f[z0:z0 + 128])
+    for y0 in range(0, 1024, 64):
+        F[:, y0:y0 + 64] = torch.fft.fft(F[:, y0:y0 + 64], dim=0)
+    M = bank.M()
+    rhs = 0.0
+    for z0 in range(0, 2048, 128):
+        rhs += torch.sum(M[z0:z0 + 128].double() * torch.abs(F[z0:z0 + 128]).double() ** 2).item()
+    rhs /= V
+    assert abs(lhs - rhs) < 1e-5 * rhs
+    F.mul_(M)
+    del M
+    for y0 in range(0, 1024, 64):
+        F[:, y0:y0 + 64] = torch.fft.ifft(F[:, y0:y0 + 64], dim=0)
+    num = den = 0.0
+    for z0 in range(0, 2048, 128):
+        ref = torch.fft.ifft2(F[z0:z0 + 128]).real.double()
+        num += torch.sum((adj[z0:z0 + 128].double() - ref) ** 2).item()
+        den += torch.sum(ref ** 2).item()
+    assert np.sqrt(num / den) < 1e-5
