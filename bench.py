@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP32_MATRIX_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+FP32_VECTOR_TFLOPS = 157.3   # MI355X FP32 vector peak (packed FP32 counted)
 
 WORKLOADS = {
     # name: (config key of the volume recipe, human label)
@@ -63,6 +64,32 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     return ap.parse_args()
+
+
+# Processing via scores keeps every score on chip, so its kernels are bound by
+# arithmetic, not by algorithmic bytes.  Algorithmic flops per orientation
+# pair and voxel of the processing kernels (5 log2 n per point of a length-n
+# DFT; 2 for the product with the bank row, 4 for the weighted accumulation;
+# 11 for the score map: 1/V scale, |u|^2, log2, exp2, the pair factor and the
+# complex scale).
+PHI_FLOPS = 11
+
+
+def process_flops_per_pair_voxel(shape, kernel):
+    nz, ny, nx = shape
+    lg = lambda n: int(round(math.log2(n)))
+    if shape == (256, 256, 256):
+        # each direction's 3D DFT is split into a frequency side (z DFT and one
+        # y step: 12 of the 24 radix-2 levels) and a natural side (the other y
+        # step and the x DFT: 12 levels)
+        half = 5 * 12
+        return {"fwd_first_mul_bank": half + 2, "fwd_last_store_scores": 2 * half + PHI_FLOPS,
+                "rec_last_accumulate": half + 4}.get(kernel)
+    if ny == nx and nx in (64, 128):
+        # z lines, then whole (y, x) planes: inverse plane DFT, Phi, forward plane DFT
+        return {"fwd_first_mul_bank": 5 * lg(nz) + 2, "fwd_last_store_scores": 2 * 5 * lg(ny * nx) + PHI_FLOPS,
+                "rec_last_accumulate": 5 * lg(nz) + 4}.get(kernel)
+    return None
 
 
 def kernel_source_digest():
@@ -235,6 +262,21 @@ def main():
     s_u = 4 if is16 else 8
     # processing via scores keeps U on chip: its algorithmic bytes are f in and the result out
     step_bytes = V * No * 2 * s_u + 8 * V if args.op == "reconstruct" else 8 * V
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic, "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_per_launch}
+    if args.op == "process":
+        fpv = process_flops_per_pair_voxel(tuple(shape), kname)
+        pairs = No // 2 if bank.paired else No
+        if fpv is None:
+            roofline = None
+        else:
+            flops = fpv * pairs * V * args.steps / launches  # average pairs per launch
+            tf = flops / (avg_ms / 1e3) / 1e12
+            roofline = {"bound": "alu", "kernel": kname, "achieved": tf, "peak": FP32_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s", "frac": tf / FP32_VECTOR_TFLOPS, "traffic": None,
+                        "avg_launch_ms": avg_ms, "alg_flops_per_launch": flops,
+                        "alg_flops_per_pair_voxel": fpv}
     breakdown = {k: {"launches": v[0], "avg_ms": round(v[1] / v[0], 4), "share": round(v[1] / sum(x[1] for x in prof.values()), 4),
                      "alg_bytes_per_launch": v[2] / v[0]} for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
 
@@ -255,9 +297,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "shape": list(shape), "n_orients": No, "L": c["L"],
                    "score_dtype": args.dtype, "batch": 1, "op": args.op},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_per_launch},
+        "roofline": roofline,
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBs": step_bytes / (ms_per_step / 1e3) / 1e9,
                           "frac": step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
         "bank_build": {"synth_ms": bank_ms, "alg_tflops": bank_flops / (bank_ms / 1e3) / 1e12 if bank_ms else None,
