@@ -10,7 +10,11 @@ subdivided icosahedron), L = 24, scores stored as complex64.
 Prints one JSON line: voxel-orientations per second, per-step p50/p99, the
 roofline of the dominant kernel (per-kernel HIP events recorded by the
 library on its launch stream over the timed region) and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+timed on a bounded sample of the same workload.  With --op process (Eq. 23,
+the score never reaches memory) the roofline is arithmetic: algorithmic
+flops of the dominant kernel against the FP32 vector peak; the profiler slot
+of the forward's last pass then times the fused inverse / Phi / forward
+kernel.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload C] [--dtype c64]
 """
