@@ -1,0 +1,76 @@
+// Test driver of the host FP64 wavelet design of libos3d (coefficients of
+// Sec. 3.2 and Eqs. 12-16, the steering matrix of Eqs. 17-19, antipodal
+// pairing, the DFT radix plans), built with g++ and the address and
+// undefined-behaviour sanitizers by tests/test_host_sanitizers.py.  It prints
+// the coefficients for the parameter grid the test compares with the oracle,
+// and checks the plans and layouts itself; any sanitizer report fails the run.
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "os3d_internal.h"
+
+using namespace os3d;
+
+int main() {
+  int bad = 0;
+  const int Ls[] = {0, 1, 2, 7, 16, 24, 40, 62, 64};
+  const double ss[] = {0.25, 0.7, 1.9};
+  const int ks[] = {0, 2, 4};
+  for (int L : Ls)
+    for (double s : ss)
+      for (int k : ks)
+        for (int coeffs = 0; coeffs < 2; ++coeffs)
+          for (int variant = 0; variant < 2; ++variant) {
+            os3d_wavelet_params p = {L, s, k, 20, 0.8, 1e-3, variant, coeffs};
+            std::vector<double> c, a;
+            wavelet_coeffs(p, c, a);
+            if ((int)c.size() != L + 1 || (int)a.size() != L + 1) ++bad;
+            std::printf("coef %d %.17g %d %d %d", L, s, k, coeffs, variant);
+            for (double v : a) std::printf(" %.17g", v);
+            std::printf("\n");
+          }
+  // steering matrix and pairing on the 42-point icosahedral set
+  std::vector<double> ico = geodesic_icosahedron(2);  // 42 unit vectors
+  const int n = (int)ico.size() / 3;
+  os3d_wavelet_params p = {24, 0.5, 2, 20, 0.8, 1e-3, OS3D_CAKE, OS3D_COEFFS_LSQ};
+  std::vector<double> c, a;
+  wavelet_coeffs(p, c, a);
+  std::vector<double> S((size_t)25 * 25 * n);
+  steering_std(p, ico.data(), n, a, S.data());
+  double sum = 0.0;
+  for (double v : S) sum += std::fabs(v);
+  std::printf("steer %d %.17g\n", n, sum);
+  std::vector<int> partner;
+  pair_orientations(ico.data(), n, partner);
+  for (int i = 0; i < n; ++i)
+    if (partner[i] < 0 || partner[partner[i]] != i) ++bad;
+  // radix plans: every supported length factors into the stages
+  int plans = 0;
+  for (int len = 2; len <= kMaxDim; ++len) {
+    if (!factor235(len)) continue;
+    std::vector<int> r = radix_schedule(len);
+    long long prod = 1;
+    for (int x : r) prod *= x;
+    if (prod != len || (int)r.size() > kMaxStages) ++bad;
+    ++plans;
+  }
+  // the contraction layout of the bank kernel addresses every (l, m) once
+  for (int L : Ls) {
+    KLayout kl = k_layout(L);
+    std::vector<int> seen(kl.K, 0);
+    for (int l = 0; l <= L; ++l)
+      for (int m = 0; m <= l; ++m) {
+        ++seen[k_index(kl, l, m, false)];
+        if (m > 0) ++seen[k_index(kl, l, m, true)];
+      }
+    int used = 0;
+    for (int v : seen) {
+      if (v > 1) ++bad;
+      used += v;
+    }
+    if (used != (L + 1) * (L + 1)) ++bad;
+  }
+  std::printf("plans %d bad %d\n", plans, bad);
+  return bad ? 1 : 0;
+}

@@ -357,6 +357,26 @@ def test_M_even_band_mean_and_positive():
     assert np.min(M[(rho <= 0.8 * np.pi) & ~nyq]) > 0.05
 
 
+def test_M_uniformity_grows_with_s_theta_and_M_falls_near_nyquist():
+    """Two qualitative statements of Sec. 3.1 made checkable: a wider
+    orientation window (larger s_theta) makes M more uniform over the band
+    (coefficient of variation, 42 orientations, L = 16), and the radial
+    window makes M small near the Nyquist frequency, which is where the
+    stabiliser eps matters."""
+    shape = (16, 16, 16)
+    n = inputs.icosahedral_orientations(1)
+    wz, wy, wx, nyq = O.freq_grid(shape)
+    rho = np.sqrt(wx ** 2 + wy ** 2 + wz ** 2)
+    band = (rho > 0) & (rho <= np.pi / 2) & ~nyq
+    cv = {}
+    for s in (0.4, 0.5, 0.7, 1.4):
+        M = O.build_bank(shape, n, O.WaveletParams(L=16, s_theta=s))["M"]
+        cv[s] = np.std(M[band]) / np.mean(M[band])
+        assert np.mean(M[(rho > 0.9 * np.pi) & ~nyq]) < 0.01
+    assert cv[0.4] > cv[0.5] > cv[0.7] > cv[1.4]
+    assert cv[0.4] > 0.1 and cv[0.7] < 0.01
+
+
 def test_pyritohedral_covariance():
     """Cyclic axis permutations and sign flips map the cubic grid and the
     icosahedral sets to themselves: W[f o R^-1](x, R n_i) = W[f](R^-1 x, n_i)."""
