@@ -199,10 +199,13 @@ os3d_status os3d_process(const os3d_bank* bank, const float* f, int32_t batch, i
                          float* f_out, void* ws, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing (not a method step: measurement support).  While
- * enabled, every launch of the transform's kernels is bracketed by two HIP
- * events recorded on its launch stream, and the algorithmic bytes that launch
- * must move are recorded with it (scores written or read: orientations x V x
- * bytes per score; the real input and output volumes: 4 V).  Enabling or
+ * enabled, a timed launch carries two HIP events that the runtime stamps
+ * with the kernel's start and end on its launch stream, and the algorithmic
+ * bytes that launch must move are recorded with it (scores written or read:
+ * orientations x V x bytes per score; the real input and output volumes:
+ * 4 V).  on = 0: off; 1: every launch; 2 + k: only the launches of kernel
+ * slot k (0 <= k < os3d_profile_count), so that timing one kernel adds
+ * nothing to the others.  Other values return OS3D_EINVAL.  Enabling or
  * disabling clears the records.  Not thread-safe; host memory only. */
 os3d_status os3d_profile_enable(int32_t on);
 

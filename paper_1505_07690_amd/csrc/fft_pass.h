@@ -11,7 +11,7 @@
 
 namespace os3d {
 
-constexpr int kMaxBatch = 16;    // orientation pairs per launch
+constexpr int kMaxBatch = 64;    // orientation pairs per launch
 
 enum LoadMode { LM_REAL = 0, LM_C = 1, LM_MULBANK = 2, LM_UIN = 3, LM_DIVM = 4 };
 enum StoreMode { SM_C = 0, SM_UOUT = 1, SM_ACCUM = 2, SM_REAL = 3, SM_PHI = 4 };

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 
+#include "launch.h"
 #include "layout4.h"
 #include "os3d_internal.h"
 
@@ -460,26 +461,26 @@ int launch_build_bank(os3d_bank* b, void* stream) {
     set_error("k_bank_synth: cannot reserve LDS");
     return OS3D_EDEVICE;
   }
-  void* tok = prof_start(st);
-  hipLaunchKernelGGL(k_bank_synth, dim3((unsigned)nblk), dim3(256), lds, st, a);
+  void* tok = prof_start(st, PROF_BANK);
+  launch_k(k_bank_synth, dim3((unsigned)nblk), dim3(256), lds, st, a);
   // algorithmic work of the contraction: 2 V (L+1)^2 n_rows flops
   prof_stop(tok, st, PROF_BANK, 0.0, 2.0 * (double)b->V * (double)(nn * nn) * (double)b->n_unique);
   int rc = check_launch("k_bank_synth");
   if (rc) return rc;
   const int nparts = 1024;
-  hipLaunchKernelGGL(k_kappa_partial, dim3(nparts), dim3(256), 0, st, b->d.Mh, b->paired, b->layout, a.Nz, a.Ny,
+  launch_k(k_kappa_partial, dim3(nparts), dim3(256), 0, st, b->d.Mh, b->paired, b->layout, a.Nz, a.Ny,
                      a.Nx, a.V, b->d.part);
   if ((rc = check_launch("k_kappa_partial"))) return rc;
-  hipLaunchKernelGGL(k_kappa_final, dim3(1), dim3(64), 0, st, b->d.part, nparts);
+  launch_k(k_kappa_final, dim3(1), dim3(64), 0, st, b->d.part, nparts);
   if ((rc = check_launch("k_kappa_final"))) return rc;
   const unsigned fin_blocks = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_bank_finalize, dim3(fin_blocks), dim3(256), 0, st, b->d.psi, b->n_unique, b->d.Mh, b->d.M,
+  launch_k(k_bank_finalize, dim3(fin_blocks), dim3(256), 0, st, b->d.psi, b->n_unique, b->d.Mh, b->d.M,
                      b->paired, b->layout, a.Nz, a.Ny, a.Nx, a.V, b->d.part + 2 * nparts);
   if ((rc = check_launch("k_bank_finalize"))) return rc;
-  hipLaunchKernelGGL(k_approx_partial, dim3(nparts), dim3(256), 0, st, b->d.psi, b->n_unique, b->paired, b->layout,
+  launch_k(k_approx_partial, dim3(nparts), dim3(256), 0, st, b->d.psi, b->n_unique, b->paired, b->layout,
                      a.Nz, a.Ny, a.Nx, a.V, b->d.part);
   if ((rc = check_launch("k_approx_partial"))) return rc;
-  hipLaunchKernelGGL(k_approx_final, dim3(1), dim3(64), 0, st, b->d.part, nparts);
+  launch_k(k_approx_final, dim3(1), dim3(64), 0, st, b->d.part, nparts);
   if ((rc = check_launch("k_approx_final"))) return rc;
   double kn[2] = {0.0, 0.0};
   if (hipMemcpyAsync(kn, b->d.part + 2 * nparts, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -503,13 +504,13 @@ int launch_approx(const os3d_bank* b, const void* U, int dtype, const float* sca
     const float* sc = scales ? scales + (long long)bi * b->n_orients : nullptr;
     float* o = f_out + (long long)bi * b->V;
     if (dtype == OS3D_C64)
-      hipLaunchKernelGGL(k_approx_reconstruct<OS3D_C64>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients, b->V,
+      launch_k(k_approx_reconstruct<OS3D_C64>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients, b->V,
                          inv_norm, o);
     else if (dtype == OS3D_BF16X2)
-      hipLaunchKernelGGL(k_approx_reconstruct<OS3D_BF16X2>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients,
+      launch_k(k_approx_reconstruct<OS3D_BF16X2>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients,
                          b->V, inv_norm, o);
     else
-      hipLaunchKernelGGL(k_approx_reconstruct<OS3D_F16X2>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients,
+      launch_k(k_approx_reconstruct<OS3D_F16X2>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients,
                          b->V, inv_norm, o);
     int rc = check_launch("k_approx_reconstruct");
     if (rc) return rc;
@@ -520,14 +521,14 @@ int launch_approx(const os3d_bank* b, const void* U, int dtype, const float* sca
 int launch_export_psi(const os3d_bank* b, int i, float* out, void* stream) {
   const float* row = b->d.psi + (long long)b->row_of[i] * b->V;
   const unsigned nb = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_export, dim3(nb), dim3(256), 0, (hipStream_t)stream, row, b->conj_of[i], b->layout,
+  launch_k(k_export, dim3(nb), dim3(256), 0, (hipStream_t)stream, row, b->conj_of[i], b->layout,
                      (int)b->dims[0], (int)b->dims[1], (int)b->dims[2], b->V, out);
   return check_launch("k_export");
 }
 
 int launch_export_M(const os3d_bank* b, float* out, void* stream) {
   const unsigned nb = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_export, dim3(nb), dim3(256), 0, (hipStream_t)stream, b->d.M, 0, b->layout, (int)b->dims[0],
+  launch_k(k_export, dim3(nb), dim3(256), 0, (hipStream_t)stream, b->d.M, 0, b->layout, (int)b->dims[0],
                      (int)b->dims[1], (int)b->dims[2], b->V, out);
   return check_launch("k_export");
 }

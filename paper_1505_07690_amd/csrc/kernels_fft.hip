@@ -19,6 +19,7 @@
 #include <cstdlib>
 
 #include "fft_pass.h"
+#include "launch.h"
 #include "layout4.h"
 
 namespace os3d {
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(256) void k_scales(const float* partial, int ntiles
 
 void launch_scales(const float* partial, int ntiles, const PassArgs& a, int dtype, float* scales, int nb,
                    hipStream_t st) {
-  hipLaunchKernelGGL(k_scales, dim3(nb), dim3(256), 0, st, partial, ntiles, a, dtype, scales);
+  launch_k(k_scales, dim3(nb), dim3(256), 0, st, partial, ntiles, a, dtype, scales);
 }
 
 static int check_launch(const char* what) {
@@ -368,8 +369,12 @@ static int tile_lines(const PassArgs& a) {
 }
 
 // ---------------------------------------------------------------------------
-// Optional per-kernel timing: HIP events recorded on the launch stream around
-// every launch, with the algorithmic bytes each launch must move.
+// Optional per-kernel timing: a pair of HIP events per launch, stamped by the
+// runtime with the kernel's start and end (launch_k), with the algorithmic
+// bytes each launch must move; every launch, or only those of one slot (so
+// that timing one kernel leaves the others' launches untouched).
+// Process-wide and meant for one host thread (the benchmark); events are
+// reused across enable calls.
 // ---------------------------------------------------------------------------
 static_assert((int)kProfBank == (int)PROF_BANK, "profiler slot of the bank kernel");
 static const char* kKernelNames[kProfCount] = {
@@ -381,36 +386,71 @@ struct ProfRec {
   int kid;
   hipEvent_t e0, e1;
   double alg_bytes, alg_flops;
+  bool launched;
 };
-static bool g_prof_on = false;
+static int g_prof_mode = 0;  // 0 off, 1 every launch, 2 + k only the launches of slot k
 static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_event_pool;
+static thread_local ProfRec* t_pending = nullptr;
 
-void* prof_start(void* stream) {
-  if (!g_prof_on) return nullptr;
+static bool take_event(hipEvent_t* e) {
+  if (!g_event_pool.empty()) {
+    *e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return true;
+  }
+  return hipEventCreate(e) == hipSuccess;
+}
+
+void* prof_start(void* stream, int kid) {
+  (void)stream;
+  if (g_prof_mode == 0 || (g_prof_mode >= 2 && kid != g_prof_mode - 2)) return nullptr;
   ProfRec* r = new ProfRec();
-  if (hipEventCreate(&r->e0) != hipSuccess || hipEventCreate(&r->e1) != hipSuccess) {
+  r->launched = false;
+  if (!take_event(&r->e0)) {
     delete r;
     return nullptr;
   }
-  (void)hipEventRecord(r->e0, (hipStream_t)stream);
+  if (!take_event(&r->e1)) {
+    g_event_pool.push_back(r->e0);
+    delete r;
+    return nullptr;
+  }
+  t_pending = r;
   return r;
 }
 
+bool prof_take(hipEvent_t* e0, hipEvent_t* e1) {
+  ProfRec* r = t_pending;
+  if (!r) return false;
+  t_pending = nullptr;
+  r->launched = true;
+  *e0 = r->e0;
+  *e1 = r->e1;
+  return true;
+}
+
 void prof_stop(void* token, void* stream, int kid, double alg_bytes, double alg_flops) {
+  (void)stream;
   if (!token) return;
   ProfRec* r = (ProfRec*)token;
-  (void)hipEventRecord(r->e1, (hipStream_t)stream);
-  r->kid = kid;
-  r->alg_bytes = alg_bytes;
-  r->alg_flops = alg_flops;
-  g_prof.push_back(*r);
+  if (t_pending == r) t_pending = nullptr;
+  if (r->launched) {
+    r->kid = kid;
+    r->alg_bytes = alg_bytes;
+    r->alg_flops = alg_flops;
+    g_prof.push_back(*r);
+  } else {  // no launch between start and stop: nothing to time
+    g_event_pool.push_back(r->e0);
+    g_event_pool.push_back(r->e1);
+  }
   delete r;
 }
 
 template <int LM, int SM, int N, int AXIS, int DT>
 static void launch_fast(const PassArgs& a, int grid_y, hipStream_t st) {
   const long long tiles = (a.lines + FastCfg<N>::W - 1) / FastCfg<N>::W;
-  hipLaunchKernelGGL((k_fast<N, AXIS, LM, SM, DT>), dim3((unsigned)tiles, grid_y), dim3(kThreads), 0, st, a);
+  launch_k((k_fast<N, AXIS, LM, SM, DT>), dim3((unsigned)tiles, grid_y), dim3(kThreads), 0, st, a);
 }
 
 template <int LM, int SM, int N, int DT>
@@ -440,13 +480,13 @@ static void launch_pass_dt(const PassArgs& a, int grid_y, hipStream_t st) {
                                 96 * 1024);
       attr_set = true;
     }
-    hipLaunchKernelGGL((k_pass<LM, SM, DT>), dim3((unsigned)tiles, grid_y), dim3(kThreads), pass_lds(a), st, a);
+    launch_k((k_pass<LM, SM, DT>), dim3((unsigned)tiles, grid_y), dim3(kThreads), pass_lds(a), st, a);
   }
 }
 
 template <int LM, int SM>
 static int run_pass(int kid, double alg, const PassArgs& a, int grid_y, hipStream_t st) {
-  void* tok = prof_start(st);
+  void* tok = prof_start(st, kid);
   if constexpr (LM == LM_UIN || SM == SM_UOUT) {
     if (a.dtype == OS3D_BF16X2) launch_pass_dt<LM, SM, OS3D_BF16X2>(a, grid_y, st);
     else if (a.dtype == OS3D_F16X2) launch_pass_dt<LM, SM, OS3D_F16X2>(a, grid_y, st);
@@ -461,7 +501,7 @@ static int run_pass(int kid, double alg, const PassArgs& a, int grid_y, hipStrea
 // Whole-plane pass of the two-pass path (kernels_plane.hip).
 template <int LM, int SM>
 static int run_plane(int kid, double alg, const PassArgs& a, int grid_y, hipStream_t st) {
-  void* tok = prof_start(st);
+  void* tok = prof_start(st, kid);
   launch_plane<LM, SM>(a, grid_y, st);
   prof_stop(tok, st, kid, alg, 0.0);
   return check_launch(kKernelNames[kid]);
@@ -582,8 +622,8 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
       if ((rc = run_pass<LM_MULBANK, SM_C>(kProfFwdFirst, 0.0, z, nb, st))) return rc;
       if (quant) {
         const long long tiles = (z.lines + tile_lines(z) - 1) / tile_lines(z);
-        void* tok = prof_start(st);
-        hipLaunchKernelGGL(k_scales, dim3(nb), dim3(256), 0, st, partial, (int)tiles, z, dtype, sc);
+        void* tok = prof_start(st, kProfScales);
+        launch_k(k_scales, dim3(nb), dim3(256), 0, st, partial, (int)tiles, z, dtype, sc);
         prof_stop(tok, st, kProfScales, 0.0, 0.0);
         if ((rc = check_launch("k_scales"))) return rc;
       }
@@ -771,7 +811,7 @@ int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, 
         x.phi_kind = phi_kind;
         x.phi_p = phi_p;
         {
-          void* tok = prof_start(st);
+          void* tok = prof_start(st, kProfFwdLast);
           launch_plane_phi(x, nb, st);
           prof_stop(tok, st, kProfFwdLast, 0.0, 0.0);
           if ((rc = check_launch("k_plane_phi"))) return rc;
@@ -863,11 +903,12 @@ int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, 
 
 int profile_enable(int on) {
   for (auto& r : g_prof) {
-    (void)hipEventDestroy(r.e0);
-    (void)hipEventDestroy(r.e1);
+    g_event_pool.push_back(r.e0);
+    g_event_pool.push_back(r.e1);
   }
   g_prof.clear();
-  g_prof_on = on != 0;
+  if (on < 0 || on >= 2 + kProfCount) return OS3D_EINVAL;
+  g_prof_mode = on;
   return OS3D_OK;
 }
 

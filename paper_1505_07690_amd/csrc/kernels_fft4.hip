@@ -24,6 +24,7 @@
 #include <algorithm>
 
 #include "fft_pass.h"
+#include "launch.h"
 #include "layout4.h"
 
 namespace os3d {
@@ -356,8 +357,8 @@ static PassArgs base_args(const os3d_bank* b, float sgn) {
 
 #define OS3D_LAUNCH4(kernel, kid, alg, a, gy)                                                  \
   do {                                                                                         \
-    void* tok_ = prof_start(st);                                                               \
-    hipLaunchKernelGGL(kernel, dim3(1024), dim3(k4Threads), 0, st, a);                         \
+    void* tok_ = prof_start(st, kid);                                                               \
+    launch_k(kernel, dim3(1024), dim3(k4Threads), 0, st, a);                         \
     prof_stop(tok_, st, kid, alg, 0.0);                                                        \
     if ((rc = check(#kernel))) return rc;                                                      \
   } while (0)
@@ -403,13 +404,13 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
       z.dst_stride = V;
       z.partial = quant ? partial : nullptr;
       {
-        void* tok = prof_start(st);
-        hipLaunchKernelGGL((k4_inv_phi<LM_MULBANK>), dim3(1024), dim3(k4Threads), 0, st, z);
+        void* tok = prof_start(st, kProfFwdFirst);
+        launch_k((k4_inv_phi<LM_MULBANK>), dim3(1024), dim3(k4Threads), 0, st, z);
         prof_stop(tok, st, kProfFwdFirst, 0.0, 0.0);
         if ((rc = check("k4_inv_phi"))) return rc;
       }
       if (quant) {
-        void* tok = prof_start(st);
+        void* tok = prof_start(st, kProfScales);
         launch_scales(partial, 1024, z, dtype, sc, nb, st);
         prof_stop(tok, st, kProfScales, 0.0, 0.0);
         if ((rc = check("k_scales"))) return rc;
@@ -423,13 +424,13 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
       x.scales = quant ? sc : nullptr;
       x.out_scale = 1.f / (float)V;
       {
-        void* tok = prof_start(st);
+        void* tok = prof_start(st, kProfFwdLast);
         if (dtype == OS3D_C64)
-          hipLaunchKernelGGL((k4_inv_nat<SM_UOUT, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_inv_nat<SM_UOUT, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else if (dtype == OS3D_BF16X2)
-          hipLaunchKernelGGL((k4_inv_nat<SM_UOUT, OS3D_BF16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_inv_nat<SM_UOUT, OS3D_BF16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else
-          hipLaunchKernelGGL((k4_inv_nat<SM_UOUT, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_inv_nat<SM_UOUT, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfFwdLast, nor * (double)V * (double)ubytes, 0.0);
         if ((rc = check("k4_inv_nat"))) return rc;
       }
@@ -467,13 +468,13 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
       x.dst_c = T;
       x.dst_stride = V;
       {
-        void* tok = prof_start(st);
+        void* tok = prof_start(st, kProfRecFirst);
         if (dtype == OS3D_C64)
-          hipLaunchKernelGGL((k4_fwd_nat<LM_UIN, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_fwd_nat<LM_UIN, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else if (dtype == OS3D_BF16X2)
-          hipLaunchKernelGGL((k4_fwd_nat<LM_UIN, OS3D_BF16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_fwd_nat<LM_UIN, OS3D_BF16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else
-          hipLaunchKernelGGL((k4_fwd_nat<LM_UIN, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_fwd_nat<LM_UIN, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfRecFirst, nor * (double)V * (double)ubytes, 0.0);
         if ((rc = check("k4_fwd_nat"))) return rc;
       }
@@ -550,8 +551,8 @@ int process4(const os3d_bank* b, const float* f, int batch, int phi_kind, float 
       x.phi_kind = phi_kind;
       x.phi_p = phi_p;
       {
-        void* tok = prof_start(st);
-        hipLaunchKernelGGL(k4_nat_phi, dim3(1024, nb), dim3(k4Threads), 0, st, x);
+        void* tok = prof_start(st, kProfFwdLast);
+        launch_k(k4_nat_phi, dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfFwdLast, 0.0, 0.0);
         if ((rc = check("k4_nat_phi"))) return rc;
       }

@@ -19,6 +19,7 @@
 #include <unordered_set>
 
 #include "fft_pass.h"
+#include "launch.h"
 
 namespace os3d {
 
@@ -355,7 +356,7 @@ static void launch_persistent(K kernel, int NP, long long ntask, size_t lds, int
   // one workgroup per CU for 128^2 planes (LDS), four for 64^2; each loops over its tasks
   const int per_cu = (NP == 128) ? 1 : 4;
   const unsigned grid = (unsigned)std::min<long long>(ntask, (long long)cu_count() * per_cu);
-  hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), lds, st, a);
+  launch_k(kernel, dim3(grid), dim3(threads), lds, st, a);
 }
 
 template <int NP, int LM, int SM, int DT>

@@ -366,7 +366,11 @@ os3d_status os3d_process(const os3d_bank* b, const float* f, int32_t batch, int3
   return (os3d_status)launch_process(b, f, batch, phi, (float)phi_power, f_out, ws, stream);
 }
 
-os3d_status os3d_profile_enable(int32_t on) { return (os3d_status)profile_enable(on); }
+os3d_status os3d_profile_enable(int32_t on) {
+  int rc = profile_enable(on);
+  if (rc) return (os3d_status)fail(rc, "os3d_profile_enable: on must be 0, 1 or 2 + a kernel slot");
+  return OS3D_OK;
+}
 
 os3d_status os3d_profile_count(int32_t* n) {
   if (!n) return (os3d_status)fail(OS3D_EINVAL, "n is NULL");

@@ -121,8 +121,9 @@ int launch_export_M(const os3d_bank* b, float* out, void* stream);
 size_t workspace_bytes(const os3d_bank* b);
 int profile_enable(int on);
 // Launch bracketing for the per-kernel timer: prof_start returns a token (or
-// null when timing is off); prof_stop records the launch under kernel slot kid.
-void* prof_start(void* stream);
+// null when timing is off) and leaves its events for the one launch that
+// follows (launch_k in launch.h); prof_stop files that launch under slot kid.
+void* prof_start(void* stream, int kid);
 void prof_stop(void* token, void* stream, int kid, double alg_bytes, double alg_flops);
 enum ProfSlot { PROF_BANK = 13 };
 int profile_get(int idx, const char** name, long long* launches, double* total_ms, double* alg_bytes,

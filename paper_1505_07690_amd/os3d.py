@@ -328,9 +328,30 @@ def unpack16(Uq, scales, dtype):
     return torch.complex(v[..., 0] * s, v[..., 1] * s)
 
 
-def profile_enable(on=True):
-    """Per-kernel HIP-event timing inside the library (clears old records)."""
-    _check(lib().os3d_profile_enable(1 if on else 0))
+def profile_enable(on=True, kernel=None):
+    """Per-kernel HIP-event timing inside the library (clears old records):
+    every launch, or with kernel=<slot name> only that kernel's launches."""
+    if not on:
+        mode = 0
+    elif kernel is None:
+        mode = 1
+    else:
+        mode = 2 + profile_slots().index(kernel)
+    _check(lib().os3d_profile_enable(mode))
+
+
+def profile_slots():
+    """Names of the library's kernel timing slots, in slot order."""
+    n = ctypes.c_int32()
+    _check(lib().os3d_profile_count(ctypes.byref(n)))
+    names = []
+    for i in range(n.value):
+        name = ctypes.c_char_p()
+        launches, ms, by, fl = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        lib().os3d_profile_get(i, ctypes.byref(name), ctypes.byref(launches), ctypes.byref(ms), ctypes.byref(by),
+                               ctypes.byref(fl))
+        names.append(name.value.decode())
+    return names
 
 
 def profile_read():

@@ -364,8 +364,9 @@ class Server:
         # jobs of the same group, oldest first, that may share this launch
         group = candidates[: self.max_batch]
         if entry is None:
-            # the footprint needs the bank's workspace size: size it on a
-            # single job first, then build the bank only if that fits
+            # the exact footprint needs the bank's workspace size: check a
+            # lower bound for a single job first, build the bank only if that
+            # fits, and size the batch exactly below
             need1 = bank_need + self.ex.job_bytes_estimate(key, 1, job.op, job.dtype)
             if need1 > self.budget:
                 self._fail_group([job], AdmissionError(
@@ -510,11 +511,12 @@ class GpuExecutor:
         return io + B * n * V * su + B * n * 4
 
     def job_bytes_estimate(self, key, B, op, dtype):
-        """Footprint before the bank exists (workspace at its largest: F, X
-        and 18 volumes of intermediates)."""
+        """A lower bound of the footprint before the bank exists: the
+        library's workspace is at least F, X and two intermediate volumes.
+        The exact footprint (job_bytes) is taken once the bank is built."""
         shape, n, L = key
         V = int(np.prod(shape))
-        return self._score_bytes(shape, n, B, op, dtype) + 18 * V * 8 + (1 << 20)
+        return self._score_bytes(shape, n, B, op, dtype) + 4 * V * 8
 
     def job_bytes(self, key, bank, B, op, dtype):
         shape, n, L = key

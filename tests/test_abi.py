@@ -131,6 +131,14 @@ def test_errors_are_status_codes():
     assert L.os3d_reconstruct_approx(None, None, 0, None, 1, None, None) == -1
     assert L.os3d_process(None, None, 1, 0, 1.5, None, None, 0, None) == -1
     assert L.os3d_free_bank(None) == 0
+    # timing modes: off, every launch, one slot; nothing else
+    nslots = ctypes.c_int32()
+    assert L.os3d_profile_count(ctypes.byref(nslots)) == 0
+    for mode in (0, 1, 2, 2 + nslots.value - 1, 0):
+        assert L.os3d_profile_enable(mode) == 0, mode
+    for mode in (-1, 2 + nslots.value):
+        assert L.os3d_profile_enable(mode) == -1, mode
+    assert os3d.profile_slots()[-1] == "bank_synth_mfma"
 
 
 def test_bank_bytes_halved_for_antipodal_sets():

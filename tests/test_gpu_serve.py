@@ -77,16 +77,17 @@ def test_tight_budget_serialises(torch):
     ex = serve.GpuExecutor(n_slots=3)
     key = (shape, 42, 16)
     bank_b = ex.bank_bytes(key)
-    V = 64 ** 3
-    # one bank, one job (score, volumes, workspace upper bound), not two jobs
-    budget = bank_b + 42 * V * 8 + 2 * V * 4 + 18 * V * 8 + (2 << 20)
+    bank = os3d.Bank(shape, serve._orients(42), serve._params(42, 16))
+    one = ex.job_bytes(key, bank, 1, "reconstruct", "c64")
+    assert ex.job_bytes_estimate(key, 1, "reconstruct", "c64") <= one  # the pre-bank check is a lower bound
+    # one bank and one job (scores, volumes, workspace), not two jobs
+    budget = bank_b + one + (2 << 20)
     vols = [inputs.tubes_device(shape, 12, (1.0, 3.0), 0.2, 0, 200 + i) for i in range(4)]
     with Server(budget, n_slots=3, max_batch=1, executor=ex) as s:
         outs = [s.submit(v, 42, 16) for v in vols]
         outs = [f.result(timeout=60) for f in outs]
         st = s.stats()
     assert st["ok"] == 4 and st["peak_bytes"] <= budget
-    bank = os3d.Bank(shape, serve._orients(42), serve._params(42, 16))
     for v, o in zip(vols, outs):
         U, _ = os3d.forward(v, bank)
         assert torch.equal(o, os3d.reconstruct(U, bank))
