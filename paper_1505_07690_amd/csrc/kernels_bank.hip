@@ -73,6 +73,7 @@ __device__ inline double radial_g(double rho2, double t_inv, int N) {
 // is the same LDS value times the point's (x + iy)^m real or imaginary part,
 // applied in registers.  Half the LDS of storing both halves: three
 // workgroups per CU.
+template <int NS>
 __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
   extern __shared__ float Ybuf[];  // [qpad_max][kYStride], then cos and sin steering rows [2][qpad_max][cols]
   __shared__ double gsh[kBankPts];
@@ -114,11 +115,20 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
   dcsh[tid] = dc;
   Msh[tid] = 0.0;
 
-  for (int c0 = 0; c0 < a.Npad; c0 += kColsPerSweep) {
-    const int ncb = min(kColsPerSweep, a.Npad - c0) / 16;
-    floatx4 acc[4][kColBlocks];
-    for (int r = 0; r < 4; ++r)
-      for (int c = 0; c < kColBlocks; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // NS sweeps of 48 columns share each order's recursion: one FP64 pass of
+  // Q_l^m per order and column group, the steering rows of every sweep
+  // staged in turn
+  // steering values prefetched in registers during the recursion (fewer when
+  // two sweeps' accumulators are live)
+  constexpr int SR = (NS == 1) ? kStageRegs : 4;
+  for (int c0 = 0; c0 < a.Npad; c0 += NS * kColsPerSweep) {
+    floatx4 acc[NS][4][kColBlocks];
+#pragma unroll
+    for (int w = 0; w < NS; ++w)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < kColBlocks; ++c) acc[w][r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     double cr = 1.0, ci = 0.0;  // (x + i y)^m of the unit frequency direction
     for (int m = 0; m <= L; ++m) {
@@ -129,14 +139,14 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
       }
       const int nq = nn - m;            // rows l = m..L
       const int qpad = (nq + 3) & ~3;
-      // issue the loads of the chunk's cos and sin steering rows (this
+      // issue the loads of the chunk's cos and sin steering rows (the first
       // sweep's columns) first, branch-free, so that they complete during
       // the recursion
       const float* Sm = a.S + (long long)koff[m] * a.Npad;
       const int half = qpad * kColsPerSweep;
-      float sv[kStageRegs];
+      float sv[SR];
 #pragma unroll
-      for (int u = 0; u < kStageRegs; ++u) {
+      for (int u = 0; u < SR; ++u) {
         const int idx = u * kBankPts + tid;
         const int part = idx >= half, id2 = idx - part * half;
         const int kr = id2 / kColsPerSweep, cc = id2 - kr * kColsPerSweep;
@@ -164,45 +174,54 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
         crsh[tid] = (float)cr;
         cish[tid] = (float)ci;
       }
-      // stage the steering rows in LDS (values past kStageRegs * 256, needed
-      // only for L > 31, are loaded here)
 #pragma unroll
-      for (int u = 0; u < kStageRegs; ++u)
-        if (u * kBankPts + tid < 2 * half) Scos[u * kBankPts + tid] = sv[u];
-      for (int idx = kStageRegs * kBankPts + tid; idx < 2 * half; idx += kBankPts) {
-        const int part = idx >= half, id2 = idx - part * half;
-        const int kr = id2 / kColsPerSweep, cc = id2 - kr * kColsPerSweep;
-        const bool ok = kr < nq && c0 + cc < a.Npad && (m > 0 || part == 0);
-        Scos[idx] = ok ? Sm[(long long)(kr + part * nq) * a.Npad + c0 + cc] : 0.f;
-      }
-      __syncthreads();
-      float crv[4], civ[4];
+      for (int w = 0; w < NS; ++w) {
+        const int cs = c0 + w * kColsPerSweep;
+        if (cs >= a.Npad) break;  // uniform
+        if (w == 0) {
+          // stage the first sweep's rows in LDS (the values past SR * 256 are
+          // loaded in the loop below)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        crv[r] = crsh[wave * 64 + r * 16 + (lane & 15)];
-        civ[r] = cish[wave * 64 + r * 16 + (lane & 15)];
-      }
-      const float* Sc = Scos;
-      const float* Ss = Scos + half;  // the sin rows follow the cos rows
-      for (int k0 = 0; k0 < qpad; k0 += 4) {
-        const int kr = k0 + (lane >> 4);
-        float q[4], bc[kColBlocks], bs[kColBlocks];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) q[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
-#pragma unroll
-        for (int c = 0; c < kColBlocks; ++c) {
-          bc[c] = Sc[kr * kColsPerSweep + c * 16 + (lane & 15)];
-          bs[c] = Ss[kr * kColsPerSweep + c * 16 + (lane & 15)];
+          for (int u = 0; u < SR; ++u)
+            if (u * kBankPts + tid < 2 * half) Scos[u * kBankPts + tid] = sv[u];
+        } else {
+          __syncthreads();  // every wave is done with the previous sweep's rows
         }
-        // all column blocks, also past Npad (zero columns); for m = 0 the sin
-        // rows are zero: no branch between the MFMAs
+        for (int idx = (w == 0 ? SR * kBankPts : 0) + tid; idx < 2 * half; idx += kBankPts) {
+          const int part = idx >= half, id2 = idx - part * half;
+          const int kr = id2 / kColsPerSweep, cc = id2 - kr * kColsPerSweep;
+          const bool ok = kr < nq && cs + cc < a.Npad && (m > 0 || part == 0);
+          Scos[idx] = ok ? Sm[(long long)(kr + part * nq) * a.Npad + cs + cc] : 0.f;
+        }
+        __syncthreads();
+        float crv[4], civ[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const float ac = q[r] * crv[r], as = q[r] * civ[r];
+          crv[r] = crsh[wave * 64 + r * 16 + (lane & 15)];
+          civ[r] = cish[wave * 64 + r * 16 + (lane & 15)];
+        }
+        const float* Sc = Scos;
+        const float* Ss = Scos + half;  // the sin rows follow the cos rows
+        for (int k0 = 0; k0 < qpad; k0 += 4) {
+          const int kr = k0 + (lane >> 4);
+          float q[4], bc[kColBlocks], bs[kColBlocks];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) q[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
 #pragma unroll
           for (int c = 0; c < kColBlocks; ++c) {
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac, bc[c], acc[r][c], 0, 0, 0);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bs[c], acc[r][c], 0, 0, 0);
+            bc[c] = Sc[kr * kColsPerSweep + c * 16 + (lane & 15)];
+            bs[c] = Ss[kr * kColsPerSweep + c * 16 + (lane & 15)];
+          }
+          // all column blocks, also past Npad (zero columns); for m = 0 the
+          // sin rows are zero: no branch between the MFMAs
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float ac = q[r] * crv[r], as = q[r] * civ[r];
+#pragma unroll
+            for (int c = 0; c < kColBlocks; ++c) {
+              acc[w][r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac, bc[c], acc[w][r][c], 0, 0, 0);
+              acc[w][r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bs[c], acc[w][r][c], 0, 0, 0);
+            }
           }
         }
       }
@@ -210,42 +229,48 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
     }
 
     // epilogue: psi_raw = g * h (DC: isotropic), bank rows, FP64 sum of squares
-    double mh[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int w = 0; w < NS; ++w) {
+      const int cs = c0 + w * kColsPerSweep;
+      if (cs >= a.Npad) break;
+      const int ncb = min(kColsPerSweep, a.Npad - cs) / 16;
+      double mh[4][4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) mh[r][i] = 0.0;
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int c = 0; c < kColBlocks; ++c) {
-      if (c >= ncb) continue;
-      const int col = c0 + c * 16 + (lane & 15);
-      const bool colok = col < a.n_rows;
+        for (int i = 0; i < 4; ++i) mh[r][i] = 0.0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int c = 0; c < kColBlocks; ++c) {
+        if (c >= ncb) continue;
+        const int col = cs + c * 16 + (lane & 15);
+        const bool colok = col < a.n_rows;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int pt = wave * 64 + r * 16 + 4 * (lane >> 4) + i;
-          const long long gp = p0 + pt;
-          double h = dcsh[pt] ? a.dc_value : (double)acc[r][c][i];
-          float v = (float)(gsh[pt] * h);
-          if (colok && gp < a.V) a.psi[(long long)col * a.V + gp] = v;
-          if (colok) mh[r][i] += (double)v * (double)v;
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int pt = wave * 64 + r * 16 + 4 * (lane >> 4) + i;
+            const long long gp = p0 + pt;
+            double h = dcsh[pt] ? a.dc_value : (double)acc[w][r][c][i];
+            float v = (float)(gsh[pt] * h);
+            if (colok && gp < a.V) a.psi[(long long)col * a.V + gp] = v;
+            if (colok) mh[r][i] += (double)v * (double)v;
+          }
         }
       }
+      // sum over the 16 lanes that share (lane >> 4): fixed xor tree, then
+      // into the point's running sum (one owner lane per point)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double s = mh[r][i];
+          s += __shfl_xor(s, 1);
+          s += __shfl_xor(s, 2);
+          s += __shfl_xor(s, 4);
+          s += __shfl_xor(s, 8);
+          if ((lane & 15) == 0) Msh[wave * 64 + r * 16 + 4 * (lane >> 4) + i] += s;
+        }
     }
-    // sum over the 16 lanes that share (lane >> 4): fixed xor tree, then
-    // into the point's running sum (one owner lane per point)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        double s = mh[r][i];
-        s += __shfl_xor(s, 1);
-        s += __shfl_xor(s, 2);
-        s += __shfl_xor(s, 4);
-        s += __shfl_xor(s, 8);
-        if ((lane & 15) == 0) Msh[wave * 64 + r * 16 + 4 * (lane >> 4) + i] += s;
-      }
   }
   __syncthreads();
   if (valid) a.Mh[p] = Msh[tid];
@@ -456,13 +481,18 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   a.maxpad = maxpad;
   size_t lds = (size_t)maxpad * (kYStride + 2 * kColsPerSweep) * sizeof(float);
   const long long nblk = (b->V + kBankPts - 1) / kBankPts;
-  if (hipFuncSetAttribute((const void*)k_bank_synth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-      hipSuccess) {
+  // one column sweep when the stored rows fit 48 columns, else two per recursion
+  const bool two = b->Npad > kColsPerSweep;
+  const void* kfn = two ? (const void*)k_bank_synth<2> : (const void*)k_bank_synth<1>;
+  if (hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
     set_error("k_bank_synth: cannot reserve LDS");
     return OS3D_EDEVICE;
   }
   void* tok = prof_start(st, PROF_BANK);
-  launch_k(k_bank_synth, dim3((unsigned)nblk), dim3(256), lds, st, a);
+  if (two)
+    launch_k(k_bank_synth<2>, dim3((unsigned)nblk), dim3(256), lds, st, a);
+  else
+    launch_k(k_bank_synth<1>, dim3((unsigned)nblk), dim3(256), lds, st, a);
   // algorithmic work of the contraction: 2 V (L+1)^2 n_rows flops
   prof_stop(tok, st, PROF_BANK, 0.0, 2.0 * (double)b->V * (double)(nn * nn) * (double)b->n_unique);
   int rc = check_launch("k_bank_synth");
