@@ -6,8 +6,11 @@ TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
 baseline of the benchmark may import this module.  It shares no code, table
 or constant generator with the HIP library: it has its own DFT (the DFT
 matrix applied per axis), its own radix-2 FFT (a cross-check), its own
-Legendre recursion, its own B-spline and its own geodesic sphere.  numpy's
-``linalg.pinv`` and ``tensordot`` are the only library primitives it calls.
+Legendre recursion, its own B-spline and its own geodesic sphere.  The
+library primitives it calls are numpy's ``linalg.pinv`` (the least-squares
+fit), ``tensordot`` (applying the DFT matrices), ``linalg.norm`` and, for
+the quadrature coefficient option, ``polynomial.legendre.leggauss`` (nodes
+and weights).
 
 Conventions (the readings of the paper this module fixes; every one is also
 a parameter or a documented constant of the library):
