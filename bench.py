@@ -319,6 +319,8 @@ def main():
         "wall_s_timed": wall,
         "source_digest": digest,
     }
+    if is16 and args.op == "reconstruct":
+        out["precision"] = precision_vs_c64(bank, fb, U[0], scales[0], rec[0], args.dtype, ws)
     if not args.no_stream_ceiling:
         out["stream_ceiling"] = stream_ceiling(dev)
     if not args.no_cpu_baseline:
@@ -326,6 +328,27 @@ def main():
         n_sample = args.cpu_orients or {"C": 12, "B": 42}[args.workload]
         out["cpu_baseline"] = cpu_baseline(args.workload, n_sample)
     print(json.dumps(out), flush=True)
+
+
+def precision_vs_c64(bank, fb, Uq, sc, rec16, dtype, ws):
+    """Untimed, after the timed steps: the same volume through complex64
+    score storage on the same GPU, and the relative L2 error of the 16-bit
+    scores (dequantised) and of their reconstruction against it."""
+    import torch
+    from paper_1505_07690_amd import os3d
+    U, _ = os3d.forward(fb, bank, ws=ws)
+    rec = os3d.reconstruct(U, bank, ws=ws)
+    num = den = 0.0
+    for i in range(U.shape[1]):
+        a = U[0, i]
+        d = os3d.unpack16(Uq[i], sc[i], dtype) - a
+        num += torch.sum(torch.view_as_real(d).double() ** 2).item()
+        den += torch.sum(torch.view_as_real(a).double() ** 2).item()
+    r = rec[0].double()
+    er = (torch.linalg.norm(rec16.double() - r) / torch.linalg.norm(r)).item()
+    del U, rec
+    return {"vs": "complex64 score storage on the same GPU (FP32 arithmetic)", "rel_l2_U": (num / den) ** 0.5,
+            "rel_l2_reconstruction": er}
 
 
 def grad_main(args, dev):
