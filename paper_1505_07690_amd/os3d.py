@@ -157,6 +157,8 @@ class Bank:
         self.orients = _orients(orients)
         self.params = _as_params(params)
         self.n_orients = self.orients.shape[0]
+        if torch.device(device).type != "cuda":
+            raise ValueError(f"a bank lives on a GPU, not on {device}")
         nbytes = bank_bytes(self.shape, self.orients, self.params)
         self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.device = self.buf.device
@@ -215,12 +217,68 @@ class Bank:
             pass
 
 
-def _batched(f, shape):
+def _same_device(t, device):
+    return t.device.type == device.type and (t.device.index or 0) == (device.index or 0)
+
+
+def _need(t, name, shape, dtypes, device):
+    """Every tensor handed to the library is checked here, before any call:
+    a pointer of the wrong device, size or type would reach the kernels."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor, got {type(t).__name__}")
+    if not _same_device(t, device):
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} must be {' or '.join(str(d) for d in dtypes)}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _workspace(ws, bank):
+    """(pointer, bytes) of the workspace; the library checks the size."""
+    ws = bank.workspace() if ws is None else ws
+    if not _same_device(ws, bank.device) or not ws.is_contiguous():
+        raise ValueError(f"the workspace must be a contiguous tensor on {bank.device}")
+    return ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()
+
+
+def _batched(f, bank):
+    import torch
     if f.dim() == 3:
+        _need(f, "f", bank.shape, (torch.float32,), bank.device)
         return f.unsqueeze(0), True
-    if f.dim() == 4 and tuple(f.shape[1:]) == shape:
+    if f.dim() == 4:
+        _need(f, "f", (f.shape[0],) + bank.shape, (torch.float32,), bank.device)
+        if f.shape[0] < 1:
+            raise ValueError("the batch of f is empty")
         return f, False
-    raise ValueError(f"expected [B, {shape}] or {shape}, got {tuple(f.shape)}")
+    raise ValueError(f"expected f of shape [B, {bank.shape}] or {bank.shape}, got {tuple(f.shape)}")
+
+
+def _scores(U, bank, dtype):
+    """U as [B, N_o, Nz, Ny, Nx] of the storage type of `dtype`."""
+    import torch
+    code = DTYPES[dtype]
+    Ub = U if U.dim() == 5 else U.unsqueeze(0)
+    _need(Ub, "U", (Ub.shape[0], bank.n_orients) + bank.shape,
+          (torch.complex64,) if code == OS3D_C64 else (torch.int32,), bank.device)
+    if Ub.shape[0] < 1:
+        raise ValueError("the batch of U is empty")
+    return Ub, code
+
+
+def _scales_arg(scales, B, bank, code):
+    import torch
+    if code == OS3D_C64:
+        return None
+    if scales is None:
+        raise ValueError("16-bit scores need their scales")
+    sc = scales if scales.dim() == 2 else scales.unsqueeze(0)
+    return _need(sc, "scales", (B, bank.n_orients), (torch.float32,), bank.device)
 
 
 def forward(f, bank, dtype="c64", ws=None, out=None, scales=None, stream=None):
@@ -228,44 +286,46 @@ def forward(f, bank, dtype="c64", ws=None, out=None, scales=None, stream=None):
     Returns (U, scales): U is complex64 [B, N_o, Nz, Ny, Nx] for "c64", else an
     int32 tensor of packed 16-bit (re, im) pairs with float32 scales [B, N_o]."""
     import torch
-    fb, single = _batched(f, bank.shape)
-    if fb.dtype != torch.float32 or not fb.is_contiguous():
-        raise ValueError("f must be a contiguous float32 tensor")
+    fb, single = _batched(f, bank)
     B = fb.shape[0]
     code = DTYPES[dtype]
+    udt = torch.complex64 if code == OS3D_C64 else torch.int32
     if out is None:
-        out = torch.empty((B, bank.n_orients) + bank.shape,
-                          dtype=torch.complex64 if code == OS3D_C64 else torch.int32, device=fb.device)
-    if code != OS3D_C64 and scales is None:
-        scales = torch.empty((B, bank.n_orients), dtype=torch.float32, device=fb.device)
-    ws = bank.workspace() if ws is None else ws
+        out = torch.empty((B, bank.n_orients) + bank.shape, dtype=udt, device=bank.device)
+    else:
+        _need(out if out.dim() == 5 else out.unsqueeze(0), "out", (B, bank.n_orients) + bank.shape, (udt,),
+              bank.device)
+    if code != OS3D_C64:
+        if scales is None:
+            scales = torch.empty((B, bank.n_orients), dtype=torch.float32, device=bank.device)
+        _scales_arg(scales, B, bank, code)
+    wp, wb = _workspace(ws, bank)
     _check(lib().os3d_forward(bank.handle, ctypes.c_void_p(fb.data_ptr()), B, ctypes.c_void_p(out.data_ptr()), code,
-                              ctypes.c_void_p(scales.data_ptr() if scales is not None else 0),
-                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
-    if single:
+                              ctypes.c_void_p(scales.data_ptr() if code != OS3D_C64 else 0),
+                              wp, wb, _stream_ptr(stream)))
+    if single and out.dim() == 5:
         out = out[0]
-        scales = scales[0] if scales is not None else None
-    return out, scales
+        scales = scales[0] if scales is not None and scales.dim() == 2 else scales
+    return out, (scales if code != OS3D_C64 else None)
+
+
+def _volume_out(out, B, bank):
+    import torch
+    if out is None:
+        return torch.empty((B,) + bank.shape, dtype=torch.float32, device=bank.device)
+    _need(out if out.dim() == 4 else out.unsqueeze(0), "out", (B,) + bank.shape, (torch.float32,), bank.device)
+    return out
 
 
 def _reduce(fn, U, bank, scales, dtype, ws, out, stream):
-    import torch
-    code = DTYPES[dtype]
-    Ub = U if U.dim() == 5 else U.unsqueeze(0)
-    if not Ub.is_contiguous():
-        raise ValueError("U must be contiguous")
-    if code == OS3D_C64 and Ub.dtype != torch.complex64:
-        raise ValueError("c64 scores must be complex64")
+    Ub, code = _scores(U, bank, dtype)
     B = Ub.shape[0]
-    if out is None:
-        out = torch.empty((B,) + bank.shape, dtype=torch.float32, device=Ub.device)
-    sc = None
-    if code != OS3D_C64:
-        sc = scales if scales.dim() == 2 else scales.unsqueeze(0)
-    ws = bank.workspace() if ws is None else ws
+    out = _volume_out(out, B, bank)
+    sc = _scales_arg(scales, B, bank, code)
+    wp, wb = _workspace(ws, bank)
     _check(fn(bank.handle, ctypes.c_void_p(Ub.data_ptr()), code, ctypes.c_void_p(sc.data_ptr() if sc is not None else 0),
-              B, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)))
-    return out if U.dim() == 5 else out[0]
+              B, ctypes.c_void_p(out.data_ptr()), wp, wb, _stream_ptr(stream)))
+    return out if U.dim() == 5 or out.dim() == 3 else out[0]
 
 
 def adjoint(U, bank, scales=None, dtype="c64", ws=None, out=None, stream=None):
@@ -280,21 +340,14 @@ def reconstruct(U, bank, scales=None, dtype="c64", ws=None, out=None, stream=Non
 
 def reconstruct_approx(U, bank, scales=None, dtype="c64", out=None, stream=None):
     """Approximate reconstruction of Eq. (6): Re(sum_i U_i) / S."""
-    import torch
-    code = DTYPES[dtype]
-    Ub = U if U.dim() == 5 else U.unsqueeze(0)
-    if not Ub.is_contiguous():
-        raise ValueError("U must be contiguous")
+    Ub, code = _scores(U, bank, dtype)
     B = Ub.shape[0]
-    if out is None:
-        out = torch.empty((B,) + bank.shape, dtype=torch.float32, device=Ub.device)
-    sc = None
-    if code != OS3D_C64:
-        sc = scales if scales.dim() == 2 else scales.unsqueeze(0)
+    out = _volume_out(out, B, bank)
+    sc = _scales_arg(scales, B, bank, code)
     _check(lib().os3d_reconstruct_approx(bank.handle, ctypes.c_void_p(Ub.data_ptr()), code,
                                          ctypes.c_void_p(sc.data_ptr() if sc is not None else 0), B,
                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
-    return out if U.dim() == 5 else out[0]
+    return out if U.dim() == 5 or out.dim() == 3 else out[0]
 
 
 PHIS = {"identity": 0, "soft_threshold": 1}
@@ -303,18 +356,15 @@ PHIS = {"identity": 0, "soft_threshold": 1}
 def process(f, bank, phi="soft_threshold", power=1.5, ws=None, out=None, stream=None):
     """Processing via scores, Eq. (23): Re W^+ Phi(W f) with a pointwise Phi
     ("identity" or "soft_threshold": |U|^power sgn(U))."""
-    import torch
-    fb, single = _batched(f, bank.shape)
-    if fb.dtype != torch.float32 or not fb.is_contiguous():
-        raise ValueError("f must be a contiguous float32 tensor")
+    fb, single = _batched(f, bank)
     B = fb.shape[0]
-    if out is None:
-        out = torch.empty((B,) + bank.shape, dtype=torch.float32, device=fb.device)
-    ws = bank.workspace() if ws is None else ws
+    out = _volume_out(out, B, bank)
+    if phi not in PHIS:
+        raise ValueError(f"phi must be one of {sorted(PHIS)}")
+    wp, wb = _workspace(ws, bank)
     _check(lib().os3d_process(bank.handle, ctypes.c_void_p(fb.data_ptr()), B, PHIS[phi], float(power),
-                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                              _stream_ptr(stream)))
-    return out[0] if single else out
+                              ctypes.c_void_p(out.data_ptr()), wp, wb, _stream_ptr(stream)))
+    return out[0] if single and out.dim() == 4 else out
 
 
 def unpack16(Uq, scales, dtype):
