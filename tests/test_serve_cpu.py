@@ -138,6 +138,30 @@ def test_admission_rejects_what_cannot_fit_and_keeps_serving():
         assert np.array_equal(small.result(timeout=5), 2 * vol((8, 8, 8), 1))
 
 
+def test_exact_footprint_checked_after_the_bank_is_built():
+    """Before a bank exists the server only knows a lower bound of a job's
+    footprint (the workspace size comes with the bank).  A job that passes
+    the bound but not the exact check is rejected once the bank is built;
+    the bank stays cached and other jobs keep running."""
+    class LowerBound(FakeExecutor):
+        def job_bytes_estimate(self, key, B, op, dtype):
+            shape, n, L = key
+            return B * n * int(np.prod(shape)) * 8  # the scores only
+
+    ex = LowerBound(2)
+    shape = (8, 8, 8)
+    V = 8 ** 3
+    budget = V * 42 * 2 + 42 * V * 8 + 2 * V * 8  # bank + scores + less than the 4 V * 8 workspace
+    with Server(budget, n_slots=2, executor=ex) as s:
+        job = s.submit(vol(shape, 5), 42, 16)
+        with pytest.raises(AdmissionError):
+            job.result(timeout=5)
+        small = s.submit(vol((4, 4, 4), 6), 12, 8)
+        assert np.array_equal(small.result(timeout=5), 2 * vol((4, 4, 4), 6))
+        st = s.stats()
+    assert ex.built[0] == (shape, 42, 16) and st["errors"].get("AdmissionError", 0) >= 1
+
+
 def test_memory_budget_serialises_jobs():
     """Room for one bank and one job: jobs wait for memory, never run two at
     a time, and all finish."""
