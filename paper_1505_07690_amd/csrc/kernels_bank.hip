@@ -30,7 +30,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBankPts = 256;   // frequency points per workgroup
 constexpr int kYStride = 272;   // LDS row stride (floats) of the K-chunk buffer
-constexpr int kColBlocks = 3;                  // 16-column MFMA blocks per sweep
+constexpr int kColBlocks = 3;                  // 16-column MFMA blocks per sweep (at most)
 constexpr int kColsPerSweep = 16 * kColBlocks;
 constexpr int kStageRegs = 11;                 // steering values prefetched per thread and chunk
 
@@ -73,7 +73,7 @@ __device__ inline double radial_g(double rho2, double t_inv, int N) {
 // is the same LDS value times the point's (x + iy)^m real or imaginary part,
 // applied in registers.  Half the LDS of storing both halves: three
 // workgroups per CU.
-template <int NS>
+template <int NS, int CB>
 __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
   extern __shared__ float Ybuf[];  // [qpad_max][kYStride], then cos and sin steering rows [2][qpad_max][cols]
   __shared__ double gsh[kBankPts];
@@ -115,20 +115,21 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
   dcsh[tid] = dc;
   Msh[tid] = 0.0;
 
-  // NS sweeps of 48 columns share each order's recursion: one FP64 pass of
+  constexpr int kCols = 16 * CB;  // columns per sweep
+  // NS sweeps of kCols columns share each order's recursion: one FP64 pass of
   // Q_l^m per order and column group, the steering rows of every sweep
   // staged in turn
   // steering values prefetched in registers during the recursion (fewer when
   // two sweeps' accumulators are live)
   constexpr int SR = (NS == 1) ? kStageRegs : 4;
-  for (int c0 = 0; c0 < a.Npad; c0 += NS * kColsPerSweep) {
-    floatx4 acc[NS][4][kColBlocks];
+  for (int c0 = 0; c0 < a.Npad; c0 += NS * kCols) {
+    floatx4 acc[NS][4][CB];
 #pragma unroll
     for (int w = 0; w < NS; ++w)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < kColBlocks; ++c) acc[w][r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < CB; ++c) acc[w][r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     double cr = 1.0, ci = 0.0;  // (x + i y)^m of the unit frequency direction
     for (int m = 0; m <= L; ++m) {
@@ -143,13 +144,13 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
       // sweep's columns) first, branch-free, so that they complete during
       // the recursion
       const float* Sm = a.S + (long long)koff[m] * a.Npad;
-      const int half = qpad * kColsPerSweep;
+      const int half = qpad * kCols;
       float sv[SR];
 #pragma unroll
       for (int u = 0; u < SR; ++u) {
         const int idx = u * kBankPts + tid;
         const int part = idx >= half, id2 = idx - part * half;
-        const int kr = id2 / kColsPerSweep, cc = id2 - kr * kColsPerSweep;
+        const int kr = id2 / kCols, cc = id2 - kr * kCols;
         const bool ok = idx < 2 * half && kr < nq && c0 + cc < a.Npad && (m > 0 || part == 0);
         const float v = Sm[ok ? (long long)(kr + part * nq) * a.Npad + c0 + cc : 0];
         sv[u] = ok ? v : 0.f;
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
       }
 #pragma unroll
       for (int w = 0; w < NS; ++w) {
-        const int cs = c0 + w * kColsPerSweep;
+        const int cs = c0 + w * kCols;
         if (cs >= a.Npad) break;  // uniform
         if (w == 0) {
           // stage the first sweep's rows in LDS (the values past SR * 256 are
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
         }
         for (int idx = (w == 0 ? SR * kBankPts : 0) + tid; idx < 2 * half; idx += kBankPts) {
           const int part = idx >= half, id2 = idx - part * half;
-          const int kr = id2 / kColsPerSweep, cc = id2 - kr * kColsPerSweep;
+          const int kr = id2 / kCols, cc = id2 - kr * kCols;
           const bool ok = kr < nq && cs + cc < a.Npad && (m > 0 || part == 0);
           Scos[idx] = ok ? Sm[(long long)(kr + part * nq) * a.Npad + cs + cc] : 0.f;
         }
@@ -204,13 +205,13 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
         const float* Ss = Scos + half;  // the sin rows follow the cos rows
         for (int k0 = 0; k0 < qpad; k0 += 4) {
           const int kr = k0 + (lane >> 4);
-          float q[4], bc[kColBlocks], bs[kColBlocks];
+          float q[4], bc[CB], bs[CB];
 #pragma unroll
           for (int r = 0; r < 4; ++r) q[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
 #pragma unroll
-          for (int c = 0; c < kColBlocks; ++c) {
-            bc[c] = Sc[kr * kColsPerSweep + c * 16 + (lane & 15)];
-            bs[c] = Ss[kr * kColsPerSweep + c * 16 + (lane & 15)];
+          for (int c = 0; c < CB; ++c) {
+            bc[c] = Sc[kr * kCols + c * 16 + (lane & 15)];
+            bs[c] = Ss[kr * kCols + c * 16 + (lane & 15)];
           }
           // all column blocks, also past Npad (zero columns); for m = 0 the
           // sin rows are zero: no branch between the MFMAs
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
           for (int r = 0; r < 4; ++r) {
             const float ac = q[r] * crv[r], as = q[r] * civ[r];
 #pragma unroll
-            for (int c = 0; c < kColBlocks; ++c) {
+            for (int c = 0; c < CB; ++c) {
               acc[w][r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac, bc[c], acc[w][r][c], 0, 0, 0);
               acc[w][r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bs[c], acc[w][r][c], 0, 0, 0);
             }
@@ -231,16 +232,16 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
     // epilogue: psi_raw = g * h (DC: isotropic), bank rows, FP64 sum of squares
 #pragma unroll
     for (int w = 0; w < NS; ++w) {
-      const int cs = c0 + w * kColsPerSweep;
+      const int cs = c0 + w * kCols;
       if (cs >= a.Npad) break;
-      const int ncb = min(kColsPerSweep, a.Npad - cs) / 16;
+      const int ncb = min(kCols, a.Npad - cs) / 16;
       double mh[4][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int i = 0; i < 4; ++i) mh[r][i] = 0.0;
 #pragma unroll
-      for (int c = 0; c < kColBlocks; ++c) {
+      for (int c = 0; c < CB; ++c) {
         if (c >= ncb) continue;
         const int col = cs + c * 16 + (lane & 15);
         const bool colok = col < a.n_rows;
@@ -479,20 +480,25 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   // LDS rows per chunk: the L + 1 - m values Q_l^m, padded to 4 (largest at m = 0)
   const int maxpad = (nn + 3) / 4 * 4;
   a.maxpad = maxpad;
-  size_t lds = (size_t)maxpad * (kYStride + 2 * kColsPerSweep) * sizeof(float);
   const long long nblk = (b->V + kBankPts - 1) / kBankPts;
-  // one column sweep when the stored rows fit 48 columns, else two per recursion
-  const bool two = b->Npad > kColsPerSweep;
-  const void* kfn = two ? (const void*)k_bank_synth<2> : (const void*)k_bank_synth<1>;
+  // the stored rows in one sweep of 32 or 48 columns, or two 48-column
+  // sweeps per recursion
+  const int cb = (b->Npad <= 32) ? 2 : 3;
+  const int ns = (b->Npad > kColsPerSweep) ? 2 : 1;
+  size_t lds = (size_t)maxpad * (kYStride + 2 * 16 * cb) * sizeof(float);
+  const void* kfn = ns == 2 ? (const void*)k_bank_synth<2, 3>
+                            : (cb == 2 ? (const void*)k_bank_synth<1, 2> : (const void*)k_bank_synth<1, 3>);
   if (hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
     set_error("k_bank_synth: cannot reserve LDS");
     return OS3D_EDEVICE;
   }
   void* tok = prof_start(st, PROF_BANK);
-  if (two)
-    launch_k(k_bank_synth<2>, dim3((unsigned)nblk), dim3(256), lds, st, a);
+  if (ns == 2)
+    launch_k(k_bank_synth<2, 3>, dim3((unsigned)nblk), dim3(256), lds, st, a);
+  else if (cb == 2)
+    launch_k(k_bank_synth<1, 2>, dim3((unsigned)nblk), dim3(256), lds, st, a);
   else
-    launch_k(k_bank_synth<1>, dim3((unsigned)nblk), dim3(256), lds, st, a);
+    launch_k(k_bank_synth<1, 3>, dim3((unsigned)nblk), dim3(256), lds, st, a);
   // algorithmic work of the contraction: 2 V (L+1)^2 n_rows flops
   prof_stop(tok, st, PROF_BANK, 0.0, 2.0 * (double)b->V * (double)(nn * nn) * (double)b->n_unique);
   int rc = check_launch("k_bank_synth");

@@ -86,13 +86,16 @@ CASES = {
                    inputs.tubes((10, 12, 8), 2, 1.2, 0.1, 0, 20)),
     "single": lambda: ((12, 8, 10), np.array([[0.0, 0.0, 1.0]]), _oracle_params(8, 12),
                        inputs.tubes((12, 8, 10), 2, 1.2, 0.1, 0, 21)),
-    # more than 48 stored rows: two column sweeps per recursion in the bank
+    # more than 48 stored rows: two 48-column sweeps per recursion in the bank
     # synthesis (81 rows of the 162-orientation set; 60 unpaired rows, the
     # second sweep partly filled)
     "ico162": lambda: ((10, 12, 8), inputs.icosahedral_orientations(2), _oracle_params(12, 162),
                        inputs.tubes((10, 12, 8), 2, 1.2, 0.1, 0, 22)),
     "rand60": lambda: ((8, 10, 12), _random_orients(60, 23), _oracle_params(8, 60),
                        inputs.tubes((8, 10, 12), 2, 1.2, 0.1, 0, 24)),
+    # 33-48 stored rows: one 48-column sweep (up to 32 rows take a 32-column sweep)
+    "rand40": lambda: ((10, 8, 12), _random_orients(40, 25), _oracle_params(10, 40),
+                       inputs.tubes((10, 8, 12), 2, 1.2, 0.1, 0, 26)),
     # small N with radix-2 only and a long axis
     "long4x6x64": lambda: ((4, 6, 64), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                            inputs.tubes((4, 6, 64), 2, 1.0, 0.1, 0, 8)),
@@ -117,7 +120,7 @@ def test_bank_and_M_parity(case):
     assert rel(psi, ob["psi_hat"]) < TOL
     assert rel(gb.M().cpu().numpy(), ob["M"]) < TOL
     assert abs(gb.kappa - ob["kappa"]) < 1e-6 * ob["kappa"]
-    assert gb.paired == (case["name"] not in ("unpaired_plate", "tetra", "single", "rand60"))
+    assert gb.paired == (case["name"] not in ("unpaired_plate", "tetra", "single", "rand60", "rand40"))
 
 
 def test_forward_parity(case):
