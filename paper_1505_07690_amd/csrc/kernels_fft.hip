@@ -772,11 +772,10 @@ int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, 
                    void* stream) {
   // the plane path transforms in place (F, X and one volume per pair); the
   // others keep the reconstruction's input in a second volume per pair
-  int nbp = b->plane ? pair_batch(b) : std::max(1, pair_batch(b) / 2);
-  {  // the same number of pairs in every launch (no short last launch)
-    const int launches = (b->n_unique + nbp - 1) / nbp;
-    nbp = (b->n_unique + launches - 1) / launches;
-  }
+  // the largest batch the workspace allows: spreading the pairs evenly over
+  // the same number of launches measured slower (a launch costs less the
+  // more pairs it carries)
+  const int nbp = b->plane ? pair_batch(b) : std::max(1, pair_batch(b) / 2);
   if (b->layout == kLayoutFour256) return process4(b, f, batch, phi_kind, phi_p, f_out, ws, nbp, stream);
   hipStream_t st = (hipStream_t)stream;
   const long long V = b->V;
