@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C", choices=sorted(WORKLOADS))
     ap.add_argument("--dtype", default="c64", choices=["c64", "bf16", "fp16"])
-    ap.add_argument("--op", default="reconstruct", choices=["reconstruct", "process"],
+    ap.add_argument("--op", default="reconstruct", choices=["reconstruct", "process", "approx"],
                     help="reconstruct: forward + reconstruction (the metric); process: processing via scores "
                          "(Eq. 23, soft threshold p = 1.5) fused so that U never reaches memory")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -228,6 +228,20 @@ def main():
 
         def step():
             os3d.process(fb, bank, "soft_threshold", 1.5, ws=ws, out=rec)
+    elif args.op == "approx":
+        # forward + approximate reconstruction (Eq. 6); the reduction kernel is
+        # timed with torch events, since the library launches it on this stream
+        approx_ev = []
+
+        def step(timed=False):
+            os3d.forward(fb, bank, dtype=args.dtype, ws=ws, out=U, scales=scales)
+            if timed:
+                e = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                e[0].record()
+            os3d.reconstruct_approx(U, bank, scales=scales, dtype=args.dtype, out=rec)
+            if timed:
+                e[1].record()
+                approx_ev.append(e)
     else:
         def step():
             os3d.forward(fb, bank, dtype=args.dtype, ws=ws, out=U, scales=scales)
@@ -252,7 +266,10 @@ def main():
     t0 = time.perf_counter()
     ev[0].record(stream)
     for k in range(args.steps):
-        step()
+        if args.op == "approx":
+            step(timed=True)
+        else:
+            step()
         ev[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -273,7 +290,7 @@ def main():
     traffic = load_traffic(kname, digest)
     s_u = 4 if is16 else 8
     # processing via scores keeps U on chip: its algorithmic bytes are f in and the result out
-    step_bytes = V * No * 2 * s_u + 8 * V if args.op == "reconstruct" else 8 * V
+    step_bytes = V * No * 2 * s_u + 8 * V if args.op in ("reconstruct", "approx") else 8 * V
     roofline = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
                 "traffic": traffic, "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_per_launch}
@@ -319,6 +336,14 @@ def main():
         "wall_s_timed": wall,
         "source_digest": digest,
     }
+    if args.op == "approx":
+        # the one-pass orientation sum: every score read once, the volume written once
+        a_ms = sum(e0.elapsed_time(e1) for e0, e1 in approx_ev) / len(approx_ev)
+        a_bytes = V * No * s_u + 4 * V
+        out["approx_roofline"] = {"bound": "hbm", "kernel": "k_approx_reconstruct", "achieved": a_bytes / (a_ms / 1e3) / 1e9,
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": a_bytes / (a_ms / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                                  "avg_launch_ms": a_ms, "alg_bytes_per_launch": a_bytes}
     if is16 and args.op == "reconstruct":
         out["precision"] = precision_vs_c64(bank, fb, U[0], scales[0], rec[0], args.dtype, ws)
     if not args.no_stream_ceiling:

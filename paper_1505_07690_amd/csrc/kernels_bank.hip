@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 
 #include "launch.h"
 #include "layout4.h"
@@ -391,27 +392,52 @@ __global__ void k_approx_final(double* part, int nparts) {
 }
 
 // f_out[b] = Re(sum_i U[b][i]) / S: the orientation integral of Eq. (6), one
-// pass over the scores, fixed summation order (deterministic).
+// pass over the scores, fixed summation order (deterministic).  A thread
+// sums VPT consecutive voxels, loading 16 bytes per orientation (two
+// complex64 or four packed 16-bit scores) when VPT > 1; the per-voxel
+// order of the sum is the same for every VPT.
 template <int DT>
+__device__ __forceinline__ float approx_re(unsigned int q) {
+  if constexpr (DT == OS3D_F16X2)
+    return __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
+  else
+    return __uint_as_float((q & 0xffffu) << 16);
+}
+
+template <int DT, int VPT>
 __global__ __launch_bounds__(256) void k_approx_reconstruct(const void* U, const float* scales, int n_orients,
                                                             long long V, float inv_norm, float* out) {
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long p = ((long long)blockIdx.x * 256 + threadIdx.x) * VPT;
   if (p >= V) return;
-  float acc = 0.f;
+  float acc[VPT];
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) acc[v] = 0.f;
+#pragma unroll 4
   for (int i = 0; i < n_orients; ++i) {
+    const long long e = (long long)i * V + p;
     if constexpr (DT == OS3D_C64) {
-      acc += ((const float2*)U)[(long long)i * V + p].x;
+      if constexpr (VPT == 2) {
+        const float4 w = *(const float4*)((const float2*)U + e);
+        acc[0] += w.x;
+        acc[1] += w.z;
+      } else {
+        acc[0] += ((const float2*)U)[e].x;
+      }
     } else {
-      const unsigned int q = ((const unsigned int*)U)[(long long)i * V + p];
-      float re;
-      if constexpr (DT == OS3D_F16X2)
-        re = __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
-      else
-        re = __uint_as_float((q & 0xffffu) << 16);
-      acc += re * scales[i];
+      const float sc = scales[i];
+      if constexpr (VPT == 4) {
+        const uint4 w = *(const uint4*)((const unsigned int*)U + e);
+        acc[0] += approx_re<DT>(w.x) * sc;
+        acc[1] += approx_re<DT>(w.y) * sc;
+        acc[2] += approx_re<DT>(w.z) * sc;
+        acc[3] += approx_re<DT>(w.w) * sc;
+      } else {
+        acc[0] += approx_re<DT>(((const unsigned int*)U)[e]) * sc;
+      }
     }
   }
-  out[p] = acc * inv_norm;
+#pragma unroll
+  for (int v = 0; v < VPT; ++v) out[p + v] = acc[v] * inv_norm;
 }
 
 // psi *= kappa; M = kappa^2 M0.
@@ -529,25 +555,40 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   return OS3D_OK;
 }
 
+template <int DT, int VPT>
+static void launch_approx_k(const void* Ub, const float* sc, const os3d_bank* b, float inv_norm, float* o,
+                            hipStream_t st) {
+  const unsigned nblk = (unsigned)((b->V / VPT + 255) / 256);
+  launch_k(k_approx_reconstruct<DT, VPT>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients, b->V, inv_norm, o);
+}
+
 int launch_approx(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out,
                   void* stream) {
   hipStream_t st = (hipStream_t)stream;
   const size_t ubytes = (dtype == OS3D_C64) ? 8 : 4;
-  const unsigned nblk = (unsigned)((b->V + 255) / 256);
   const float inv_norm = (float)(1.0 / b->approx_norm);
   for (int bi = 0; bi < batch; ++bi) {
     const void* Ub = (const char*)U + (size_t)bi * b->n_orients * b->V * ubytes;
     const float* sc = scales ? scales + (long long)bi * b->n_orients : nullptr;
     float* o = f_out + (long long)bi * b->V;
-    if (dtype == OS3D_C64)
-      launch_k(k_approx_reconstruct<OS3D_C64>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients, b->V,
-                         inv_norm, o);
-    else if (dtype == OS3D_BF16X2)
-      launch_k(k_approx_reconstruct<OS3D_BF16X2>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients,
-                         b->V, inv_norm, o);
-    else
-      launch_k(k_approx_reconstruct<OS3D_F16X2>, dim3(nblk), dim3(256), 0, st, Ub, sc, b->n_orients,
-                         b->V, inv_norm, o);
+    // 16-byte loads when every orientation's row starts 16-byte aligned
+    const bool al = ((uintptr_t)Ub % 16) == 0;
+    if (dtype == OS3D_C64) {
+      if (al && b->V % 2 == 0)
+        launch_approx_k<OS3D_C64, 2>(Ub, sc, b, inv_norm, o, st);
+      else
+        launch_approx_k<OS3D_C64, 1>(Ub, sc, b, inv_norm, o, st);
+    } else if (dtype == OS3D_BF16X2) {
+      if (al && b->V % 4 == 0)
+        launch_approx_k<OS3D_BF16X2, 4>(Ub, sc, b, inv_norm, o, st);
+      else
+        launch_approx_k<OS3D_BF16X2, 1>(Ub, sc, b, inv_norm, o, st);
+    } else {
+      if (al && b->V % 4 == 0)
+        launch_approx_k<OS3D_F16X2, 4>(Ub, sc, b, inv_norm, o, st);
+      else
+        launch_approx_k<OS3D_F16X2, 1>(Ub, sc, b, inv_norm, o, st);
+    }
     int rc = check_launch("k_approx_reconstruct");
     if (rc) return rc;
   }
