@@ -571,8 +571,10 @@ int launch_approx(const os3d_bank* b, const void* U, int dtype, const float* sca
     const void* Ub = (const char*)U + (size_t)bi * b->n_orients * b->V * ubytes;
     const float* sc = scales ? scales + (long long)bi * b->n_orients : nullptr;
     float* o = f_out + (long long)bi * b->V;
-    // 16-byte loads when every orientation's row starts 16-byte aligned
-    const bool al = ((uintptr_t)Ub % 16) == 0;
+    // 16-byte loads when every orientation's row starts 16-byte aligned and
+    // the volume is large enough to keep the GPU busy with fewer threads
+    // (at 128^3 one voxel per thread measured faster: 0.16 against 0.20 ms)
+    const bool al = ((uintptr_t)Ub % 16) == 0 && b->V >= (8LL << 20);
     if (dtype == OS3D_C64) {
       if (al && b->V % 2 == 0)
         launch_approx_k<OS3D_C64, 2>(Ub, sc, b, inv_norm, o, st);

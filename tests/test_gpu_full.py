@@ -69,6 +69,9 @@ def test_full_size_against_oracle(torch, shape, level, L):
     U, _ = os3d.forward(f, gb)
     Uo = O.forward(vol.astype(np.float64), ob)
     assert rel(U.cpu().numpy(), Uo) < TOL
+    # approximate reconstruction (Eq. 6); at 256^3 the reduction loads 16 bytes per orientation
+    approx_o = O.reconstruct_approx(Uo, ob)
+    assert rel(os3d.reconstruct_approx(U, gb).cpu().numpy(), approx_o) < TOL
     del U
     # reconstruction and adjoint of a general complex score
     Ur = _complex_scores(len(n), shape, 5)
@@ -91,6 +94,8 @@ def test_full_size_against_oracle(torch, shape, level, L):
         assert rel(os3d.unpack16(Uq, sc, fmt).cpu().numpy(), Uo) < bound
         rq = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
         assert rel(rq, O.reconstruct(Uo, ob)) < bound
+        ra = os3d.reconstruct_approx(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
+        assert rel(ra, approx_o) < bound
         del Uq
 
 

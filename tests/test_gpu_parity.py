@@ -258,6 +258,7 @@ def test_approximate_reconstruction_parity(case):
         got16 = os3d.reconstruct_approx(Uq, case["gb"], scales=sc, dtype=fmt).cpu().numpy()
         assert rel(got16, want) < bound, fmt
     # a score tensor that starts off the 16-byte grid takes the one-voxel loads
+    # (as do volumes below 2^23 voxels; the full-size tests cover the other path)
     Ub = torch.empty(Un32.size + 2, dtype=torch.complex64, device="cuda")
     Uo = Ub[1:1 + Un32.size].view(Un32.shape)
     Uo.copy_(torch.from_numpy(Un32).cuda())
