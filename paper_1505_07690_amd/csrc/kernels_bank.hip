@@ -409,36 +409,43 @@ __global__ __launch_bounds__(256) void k_approx_reconstruct(const void* U, const
                                                             long long V, float inv_norm, float* out) {
   const long long p = ((long long)blockIdx.x * 256 + threadIdx.x) * VPT;
   if (p >= V) return;
-  float acc[VPT];
+  if constexpr (VPT == 1) {  // one voxel per thread: the plain loop measured fastest
+    float acc = 0.f;
+    for (int i = 0; i < n_orients; ++i) {
+      const long long e = (long long)i * V + p;
+      if constexpr (DT == OS3D_C64)
+        acc += ((const float2*)U)[e].x;
+      else
+        acc += approx_re<DT>(((const unsigned int*)U)[e]) * scales[i];
+    }
+    out[p] = acc * inv_norm;
+  } else {
+    float acc[VPT];
 #pragma unroll
-  for (int v = 0; v < VPT; ++v) acc[v] = 0.f;
+    for (int v = 0; v < VPT; ++v) acc[v] = 0.f;
 #pragma unroll 4
-  for (int i = 0; i < n_orients; ++i) {
-    const long long e = (long long)i * V + p;
-    if constexpr (DT == OS3D_C64) {
-      if constexpr (VPT == 2) {
+    for (int i = 0; i < n_orients; ++i) {
+      const long long e = (long long)i * V + p;
+      if constexpr (DT == OS3D_C64) {
+        static_assert(VPT == 2, "complex64 scores: two per 16-byte load");
         const float4 w = *(const float4*)((const float2*)U + e);
         acc[0] += w.x;
         acc[1] += w.z;
       } else {
-        acc[0] += ((const float2*)U)[e].x;
-      }
-    } else {
-      const float sc = scales[i];
-      if constexpr (VPT == 4) {
+        static_assert(VPT == 4, "16-bit scores: four per 16-byte load");
+        const float sc = scales[i];
         const uint4 w = *(const uint4*)((const unsigned int*)U + e);
         acc[0] += approx_re<DT>(w.x) * sc;
         acc[1] += approx_re<DT>(w.y) * sc;
         acc[2] += approx_re<DT>(w.z) * sc;
         acc[3] += approx_re<DT>(w.w) * sc;
-      } else {
-        acc[0] += approx_re<DT>(((const unsigned int*)U)[e]) * sc;
       }
     }
-  }
 #pragma unroll
-  for (int v = 0; v < VPT; ++v) out[p + v] = acc[v] * inv_norm;
+    for (int v = 0; v < VPT; ++v) out[p + v] = acc[v] * inv_norm;
+  }
 }
+
 
 // psi *= kappa; M = kappa^2 M0.
 __global__ __launch_bounds__(256) void k_bank_finalize(float* psi, int n_rows, double* Mh, float* M, int paired,
