@@ -76,7 +76,7 @@ __device__ inline double radial_g(double rho2, double t_inv, int N) {
 // workgroups per CU.
 template <int NS, int CB>
 __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
-  extern __shared__ float Ybuf[];  // [qpad_max][kYStride], then cos and sin steering rows [2][qpad][48]
+  extern __shared__ float Ybuf[];  // [qpad_max][kYStride], then cos and sin steering rows [2][qpad_max][cols]
   __shared__ double gsh[kBankPts];
   __shared__ double Msh[kBankPts];
   __shared__ float crsh[kBankPts], cish[kBankPts];
@@ -117,11 +117,6 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
   Msh[tid] = 0.0;
 
   constexpr int kCols = 16 * CB;  // columns per sweep
-  // LDS row stride of the staged steering rows: 48 floats also for 32
-  // columns, so the four rows one MFMA operand load spans start on distinct
-  // bank groups (a stride of 32 makes two of them collide)
-  constexpr int kSS = 48;
-  static_assert(kCols <= kSS, "a staged row fits its stride");
   // NS sweeps of kCols columns share each order's recursion: one FP64 pass of
   // Q_l^m per order and column group, the steering rows of every sweep
   // staged in turn
@@ -189,13 +184,8 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
           // stage the first sweep's rows in LDS (the values past SR * 256 are
           // loaded in the loop below)
 #pragma unroll
-          for (int u = 0; u < SR; ++u) {
-            const int idx = u * kBankPts + tid;
-            const int part = idx >= half, id2 = idx - part * half;
-            const int kr = id2 / kCols;
-            // = part * qpad * kSS + kr * kSS + cc (idx itself when kCols = kSS)
-            if (idx < 2 * half) Scos[idx + (kSS - kCols) * (kr + part * qpad)] = sv[u];
-          }
+          for (int u = 0; u < SR; ++u)
+            if (u * kBankPts + tid < 2 * half) Scos[u * kBankPts + tid] = sv[u];
         } else {
           __syncthreads();  // every wave is done with the previous sweep's rows
         }
@@ -203,7 +193,7 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
           const int part = idx >= half, id2 = idx - part * half;
           const int kr = id2 / kCols, cc = id2 - kr * kCols;
           const bool ok = kr < nq && cs + cc < a.Npad && (m > 0 || part == 0);
-          Scos[idx + (kSS - kCols) * (kr + part * qpad)] = ok ? Sm[(long long)(kr + part * nq) * a.Npad + cs + cc] : 0.f;
+          Scos[idx] = ok ? Sm[(long long)(kr + part * nq) * a.Npad + cs + cc] : 0.f;
         }
         __syncthreads();
         float crv[4], civ[4];
@@ -213,7 +203,7 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
           civ[r] = cish[wave * 64 + r * 16 + (lane & 15)];
         }
         const float* Sc = Scos;
-        const float* Ss = Scos + qpad * kSS;  // the sin rows follow the cos rows
+        const float* Ss = Scos + half;  // the sin rows follow the cos rows
         for (int k0 = 0; k0 < qpad; k0 += 4) {
           const int kr = k0 + (lane >> 4);
           float q[4], bc[CB], bs[CB];
@@ -221,8 +211,8 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
           for (int r = 0; r < 4; ++r) q[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
 #pragma unroll
           for (int c = 0; c < CB; ++c) {
-            bc[c] = Sc[kr * kSS + c * 16 + (lane & 15)];
-            bs[c] = Ss[kr * kSS + c * 16 + (lane & 15)];
+            bc[c] = Sc[kr * kCols + c * 16 + (lane & 15)];
+            bs[c] = Ss[kr * kCols + c * 16 + (lane & 15)];
           }
           // all column blocks, also past Npad (zero columns); for m = 0 the
           // sin rows are zero: no branch between the MFMAs
@@ -528,7 +518,7 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   // sweeps per recursion
   const int cb = (b->Npad <= 32) ? 2 : 3;
   const int ns = (b->Npad > kColsPerSweep) ? 2 : 1;
-  size_t lds = (size_t)maxpad * (kYStride + 2 * 48) * sizeof(float);  // the staged rows' stride is 48
+  size_t lds = (size_t)maxpad * (kYStride + 2 * 16 * cb) * sizeof(float);
   const void* kfn = ns == 2 ? (const void*)k_bank_synth<2, 3>
                             : (cb == 2 ? (const void*)k_bank_synth<1, 2> : (const void*)k_bank_synth<1, 3>);
   if (hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
