@@ -12,6 +12,12 @@ fit), ``tensordot`` (applying the DFT matrices), ``linalg.norm`` and, for
 the quadrature coefficient option, ``polynomial.legendre.leggauss`` (nodes
 and weights).
 
+Parity unpinned (nothing outside this module fixes the value): the absolute
+level of the least-squares coefficients c_l of ``sh_coeffs_A`` (the paper
+prints none; they are only bounded against the quadrature projection of
+``sh_coeffs_A_quadrature``, which has closed-form pins), and the uniformity
+of M over the band (only its band mean is fixed, through kappa).
+
 Conventions (the readings of the paper this module fixes; every one is also
 a parameter or a documented constant of the library):
 
