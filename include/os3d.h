@@ -150,7 +150,11 @@ os3d_status os3d_get_bank_info(const os3d_bank* bank, os3d_bank_info* info);
  * caller's orientation i into psi_dev (device). */
 os3d_status os3d_bank_psi(const os3d_bank* bank, int32_t i, float* psi_dev, void* stream);
 
-/* Writes M (float32 [Nz][Ny][Nx], natural DFT index order) into M_dev (device). */
+/* Writes M[k] = sum_i psi_hat_i[k]^2, the discrete stability function of
+ * Eq. (9) with its constants absorbed into kappa (float32 [Nz][Ny][Nx],
+ * natural DFT index order), into M_dev (device, caller-owned).  The copy
+ * is enqueued on `stream`.  kappa and the library's own M (in its internal
+ * frequency order) are reported by os3d_get_bank_info. */
 os3d_status os3d_bank_M(const os3d_bank* bank, float* M_dev, void* stream);
 
 /* Bytes of workspace that os3d_forward / os3d_adjoint / os3d_reconstruct /

@@ -54,7 +54,8 @@ __all__ = [
     "cake_coeffs", "angular_profile", "freq_grid", "steering_matrix",
     "build_bank", "bank_values", "band_kappa", "forward", "adjoint", "reconstruct",
     "forward_bruteforce", "spatial_wavelets", "quantize_scores", "fit_zonal", "approx_norm",
-    "reconstruct_approx", "soft_threshold", "process",
+    "reconstruct_approx", "soft_threshold", "process", "freq_at", "band_kappa_streamed",
+    "M_at", "bank_row", "score_scale_bound", "score_scales",
 ]
 
 
@@ -495,19 +496,33 @@ def _bf16_round(x32):
     return r.astype(np.uint32).view(np.float32)
 
 
-def quantize_scores(U, fmt):
-    """Store U_i / s_i as a pair of 16-bit floats (round to nearest even) with
-    s_i a power of two: the largest |Re|, |Im| of U_i maps into [2^14, 2^15)
-    for fp16 and into [0.5, 1) for bf16.  Returns (dequantised values, s)."""
+def score_scale_bound(F, psi_hat_i):
+    """Bound of max |Re U_i|, |Im U_i| known before the inverse DFT: since
+    U_i = IDFT(psi_hat_i F), every |U_i[x]| <= (1/V) sum_k |psi_hat_i[k] F[k]|."""
+    F = np.asarray(F)
+    return float(np.sum(np.abs(np.asarray(psi_hat_i) * F)) / F.size)
+
+
+def score_scales(bounds, fmt):
+    """Per-orientation power-of-two scale of 16-bit storage from the bounds
+    of score_scale_bound: s_i = 2^e_i with bound_i = m 2^e_i, m in [0.5, 1)
+    (the smallest power of two above the bound), for bf16; 2^(e_i - 15) for
+    fp16, so that U_i / s_i stays below 2^15 < 65504."""
+    out = np.ones(len(bounds))
+    for i, b in enumerate(bounds):
+        if b > 0:
+            e = math.frexp(b)[1]
+            out[i] = math.ldexp(1.0, e - 15 if fmt == "fp16" else e)
+    return out
+
+
+def quantize_scores(U, fmt, s):
+    """Store U_i / s_i as a pair of 16-bit floats (round to nearest even)
+    with the per-orientation scales s (score_scales).  Returns the
+    dequantised values."""
     U = np.asarray(U)
-    No = U.shape[0]
-    s = np.ones(No)
     out = np.empty_like(U, dtype=np.complex128)
-    top = 15 if fmt == "fp16" else 0
-    for i in range(No):
-        m = max(np.abs(U[i].real).max(), np.abs(U[i].imag).max())
-        e = math.frexp(m)[1] if m > 0 else 0  # m = f 2^e, f in [0.5, 1)
-        s[i] = math.ldexp(1.0, e - top)
+    for i in range(U.shape[0]):
         re = (U[i].real / s[i]).astype(np.float32)
         im = (U[i].imag / s[i]).astype(np.float32)
         if fmt == "fp16":
@@ -517,5 +532,63 @@ def quantize_scores(U, fmt):
         else:
             raise ValueError(fmt)
         out[i] = (re + 1j * im) * s[i]
-    return out, s
+    return out
 
+
+# ---------------------------------------------------------------------------
+# The same bank quantities without the full grid in memory (large volumes)
+# ---------------------------------------------------------------------------
+
+def freq_at(shape, idx):
+    """omega_z, omega_y, omega_x and the Nyquist-plane flag at flat frequency
+    indices idx (natural order, x fastest)."""
+    nz, ny, nx = shape
+    idx = np.asarray(idx, dtype=np.int64)
+    kz, r = np.divmod(idx, ny * nx)
+    ky, kx = np.divmod(r, nx)
+    (wz, qz), (wy, qy), (wx, qx) = _axis_omega(nz), _axis_omega(ny), _axis_omega(nx)
+    return wz[kz], wy[ky], wx[kx], qz[kz] | qy[ky] | qx[kx]
+
+
+def _band_indices(shape):
+    """Flat indices of the kappa band (0 < rho <= rho_N / 2, no Nyquist plane)."""
+    wz, wy, wx, nyq = freq_grid(shape)
+    rho2 = wx * wx + wy * wy + wz * wz
+    band = (rho2 > 0) & (rho2 <= (RHO_N / 2) ** 2) & ~nyq
+    return np.flatnonzero(band)
+
+
+def band_kappa_streamed(shape, orients, a, params, chunk=1 << 17):
+    """kappa of build_bank (the band mean of sum_i (g h_i)^2 to the power
+    -1/2) visiting only the band's frequencies, a chunk at a time."""
+    idx = _band_indices(shape)
+    if idx.size == 0:
+        raise ValueError(f"the normalisation band of grid {shape} is empty (some dim must be >= 4)")
+    tot = 0.0
+    for c0 in range(0, idx.size, chunk):
+        wz, wy, wx, nyq = freq_at(shape, idx[c0:c0 + chunk])
+        raw = bank_values(wz, wy, wx, nyq, orients, a, params)
+        tot += float(np.sum(raw * raw))
+    return 1.0 / math.sqrt(tot / idx.size)
+
+
+def M_at(shape, idx, orients, a, params, kappa, chunk=1 << 15):
+    """M = sum_i psi_hat_i^2 (Eq. 9) at flat frequency indices idx."""
+    idx = np.asarray(idx, dtype=np.int64)
+    out = np.empty(idx.size)
+    for c0 in range(0, idx.size, chunk):
+        wz, wy, wx, nyq = freq_at(shape, idx[c0:c0 + chunk])
+        raw = bank_values(wz, wy, wx, nyq, orients, a, params)
+        out[c0:c0 + chunk] = kappa * kappa * np.sum(raw * raw, axis=0)
+    return out
+
+
+def bank_row(shape, orient, a, params, kappa, slab=16):
+    """psi_hat of one orientation over the whole grid [Nz][Ny][Nx] (kappa
+    times g h, build_bank's row), evaluated a z-slab at a time."""
+    wz, wy, wx, nyq = freq_grid(shape)
+    out = np.empty(tuple(shape))
+    n = np.asarray(orient, dtype=np.float64)[None]
+    for z0 in range(0, shape[0], slab):
+        out[z0:z0 + slab] = kappa * bank_values(wz[z0:z0 + slab], wy, wx, nyq[z0:z0 + slab], n, a, params)[0]
+    return out

@@ -22,16 +22,33 @@ FLAGS = [
 
 
 def build(verbose=False):
+    """Compiles every source to an object in a temporary folder (in
+    parallel), then links libos3d.so."""
+    import concurrent.futures
+    import tempfile
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = OUT + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-I", CSRC, "-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libos3d.so")
+    with tempfile.TemporaryDirectory(prefix="os3d_build_") as d:
+        def compile_one(src):
+            obj = os.path.join(d, os.path.splitext(src)[0] + ".o")
+            cmd = [hipcc] + [f for f in FLAGS if f != "-shared"] + ["-c", "-I", CSRC, "-o", obj,
+                                                                  os.path.join(CSRC, src)]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                sys.stderr.write(r.stdout + r.stderr)
+                raise RuntimeError(f"hipcc failed compiling {src}")
+            return obj
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as pool:
+            objs = list(pool.map(compile_one, SOURCES))
+        cmd = [hipcc] + FLAGS + ["-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed linking libos3d.so")
     os.replace(tmp, OUT)
     return OUT
 

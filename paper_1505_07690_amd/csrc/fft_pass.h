@@ -152,14 +152,20 @@ __device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long 
 // out_scale = 1/V), times 2 for a stored antipodal pair: for real f the pair
 // contributes Phi(U_n) + conj(Phi(U_-n)) = 2 Phi(U_n) to the reconstruction.
 // |U|^(p-1) = 2^((p-1)/2 log2 |U|^2) with the hardware base-2 logarithm
-// and exponential (about 1 ulp each; powf costs ~170 instructions).
+// and exponential (about 1 ulp each; powf costs ~170 instructions).  The
+// hardware logarithm flushes denormal inputs to zero, so a score whose
+// components are both below 2^-60 is scaled by 2^96 before it is squared
+// (every such |U|^2, down to the smallest denormal component, is then a
+// normal number) and log2 |U|^2 is corrected by -192.
 __device__ __forceinline__ float2 phi_apply(const PassArgs& a, int j, float2 v) {
   const float2 u = cscale(v, a.out_scale);
   const float mult = (a.ob[j] >= 0) ? 2.f : 1.f;
   if (a.phi_kind == 1) {
-    const float m2 = u.x * u.x + u.y * u.y;
-    const float f = __builtin_amdgcn_exp2f(0.5f * (a.phi_p - 1.f) * __builtin_amdgcn_logf(m2));
-    return cscale(u, (m2 > 0.f) ? mult * f : 0.f);
+    const bool tiny = fmaxf(fabsf(u.x), fabsf(u.y)) < 0x1p-60f;
+    const float2 w = tiny ? cscale(u, 0x1p96f) : u;
+    const float l2 = __builtin_amdgcn_logf(w.x * w.x + w.y * w.y) - (tiny ? 192.f : 0.f);
+    const float f = __builtin_amdgcn_exp2f(0.5f * (a.phi_p - 1.f) * l2);
+    return cscale(u, (u.x != 0.f || u.y != 0.f) ? mult * f : 0.f);
   }
   return cscale(u, mult);
 }

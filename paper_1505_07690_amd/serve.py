@@ -14,9 +14,12 @@ A scheduler thread:
   launch (the batch dimension of the C ABI);
 * keeps wavelet banks cached on the device per key, counts their bytes
   against the same budget, and drops the least recently used idle bank when
-  a new one needs the room;
+  a new one needs the room; a missing bank is built by a thread of its own,
+  so that launches keep being reaped and admitted meanwhile;
 * lets jobs run concurrently on different streams and resolves each job's
-  Future as soon as its launch has finished on the device;
+  Future as soon as its launch has finished on the device, handing the
+  output over to the stream the job was submitted from (the allocator does
+  not reuse its memory before that stream's work on it is done);
 * rejects a job that cannot fit even on an idle server (AdmissionError),
   fails only the affected jobs when a bank build or a launch raises, honours
   Future.cancel() before admission and a per-job timeout while pending, and
@@ -69,6 +72,7 @@ class _Job:
     t_submit: float
     deadline: float | None
     ready: object = None          # device event: the input volume is complete
+    consumer: object = None       # the submitting thread's stream (where the result is used)
     t_admit: float | None = None
     t_done: float | None = None
     batch: int = 0
@@ -85,6 +89,9 @@ class _BankEntry:
     nbytes: int
     refs: int = 0
     last_used: float = 0.0
+    launches: int = 0             # launches that have used it
+    building: bool = False        # a builder thread is synthesising it
+    error: object = None          # the build's exception, if it failed
 
 
 @dataclass(eq=False)
@@ -143,6 +150,7 @@ class Server:
         self.bank_hits = 0
         self.bank_misses = 0
         self.bank_evictions = 0
+        self.bank_build_s = []
         self.records = []
         self.errors = collections.Counter()
         self.error_examples = {}
@@ -171,6 +179,8 @@ class Server:
         job = _Job(next(self._ids), key, volume, op, dtype, phi, float(power), fut, now,
                    None if timeout is None else now + float(timeout))
         job.ready = self.ex.input_ready(volume)
+        if hasattr(self.ex, "consumer_stream"):
+            job.consumer = self.ex.consumer_stream(volume)
         with self._cv:
             if self._closing:
                 raise RuntimeError("server is closed")
@@ -200,6 +210,8 @@ class Server:
         out = dict(jobs=len(self.records), ok=len(ok), failed=len(self.records) - len(ok),
                    bank_hits=self.bank_hits, bank_misses=self.bank_misses, bank_evictions=self.bank_evictions,
                    bank_hit_rate=self.bank_hits / max(1, self.bank_hits + self.bank_misses),
+                   bank_builds=len(self.bank_build_s),
+                   bank_build_ms_max=1e3 * max(self.bank_build_s, default=0.0),
                    peak_bytes=self.peak_bytes, errors=dict(self.errors),
                    error_examples=dict(self.error_examples))
         if ok:
@@ -254,6 +266,8 @@ class Server:
                                     job.t_admit if job.t_admit is not None else now, now, job.batch, ok))
         job.volume = None
         if ok:
+            if job.consumer is not None:
+                self.ex.hand_over(result, job.consumer)
             job.future.set_result(result)
         else:
             name = type(exc).__name__
@@ -353,7 +367,13 @@ class Server:
     def _try_admit(self, job, candidates):
         key = job.key
         entry = self._banks.get(key)
-        hit = entry is not None
+        if entry is not None and entry.building:
+            return False  # its builder thread has not finished
+        if entry is not None and entry.error is not None:
+            self._banks.pop(key)
+            self._account(-entry.nbytes)
+            self._fail_group([j for j in self._pending if j.key == key], entry.error)
+            return True
         bank_need = 0
         if entry is None:
             try:
@@ -361,12 +381,9 @@ class Server:
             except Exception as e:
                 self._fail_group([j for j in self._pending if j.key == key], e)
                 return True
-        # jobs of the same group, oldest first, that may share this launch
-        group = candidates[: self.max_batch]
-        if entry is None:
             # the exact footprint needs the bank's workspace size: check a
-            # lower bound for a single job first, build the bank only if that
-            # fits, and size the batch exactly below
+            # lower bound for a single job first, and build the bank (on a
+            # thread of its own) only if that fits
             need1 = bank_need + self.ex.job_bytes_estimate(key, 1, job.op, job.dtype)
             if need1 > self.budget:
                 self._fail_group([job], AdmissionError(
@@ -374,17 +391,14 @@ class Server:
                 return True
             if not self._evict_for(need1, key):
                 return self._maybe_reject(job, need1)
-            try:
-                bank = self.ex.build_bank(key, self._free_slots[0])
-            except Exception as e:
-                self._fail_group([j for j in self._pending if j.key == key], e)
-                return True
-            entry = _BankEntry(bank, bank_need)
+            entry = _BankEntry(None, bank_need, refs=1, building=True)
             self._banks[key] = entry
             self._account(bank_need)
             self.bank_misses += 1
-        else:
-            self._banks.move_to_end(key)
+            threading.Thread(target=self._build, args=(key, entry), name="os3d-bank", daemon=True).start()
+            return True
+        self._banks.move_to_end(key)
+        group = candidates[: self.max_batch]
         # largest prefix of the group whose footprint fits (and stays within
         # batch_bytes when it has more than one job)
         n = len(group)
@@ -426,10 +440,26 @@ class Server:
                 self._finish(j, False, time.perf_counter(), exc=e)
             return True
         entry.refs += 1
-        self.bank_hits += int(hit)
+        self.bank_hits += int(entry.launches > 0)
+        entry.launches += 1
         self._account(need)
         self._inflight.append(_Launch(slot, batch, handle, need, entry))
         return True
+
+    def _build(self, key, entry):
+        """Builder thread: synthesise one bank, then wake the scheduler."""
+        t0 = time.perf_counter()
+        try:
+            bank, err = self.ex.build_bank(key), None
+        except Exception as e:
+            bank, err = None, e
+        with self._cv:
+            entry.bank, entry.error = bank, err
+            entry.building = False
+            entry.refs -= 1
+            entry.last_used = time.perf_counter()
+            self.bank_build_s.append(entry.last_used - t0)
+            self._cv.notify()
 
     def _maybe_reject(self, job, need):
         """A job that does not fit now waits, unless nothing is running and
@@ -474,6 +504,7 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.n_slots = int(n_slots)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(self.n_slots)]
+        self.build_stream = torch.cuda.Stream(device=self.device)
 
     def input_ready(self, volume):
         torch = self.torch
@@ -488,15 +519,30 @@ class GpuExecutor:
         shape, n, L = key
         return os3d.bank_bytes(shape, _orients(n), _params(n, L))
 
-    def build_bank(self, key, slot):
+    def build_bank(self, key):
+        """Synthesise a bank on the executor's build stream (called from a
+        builder thread); launches wait for its `ready` event."""
         from . import os3d
         shape, n, L = key
-        s = self.streams[slot]
-        with self.torch.cuda.stream(s):
+        s = self.build_stream
+        with self.torch.cuda.device(self.device), self.torch.cuda.stream(s):
             bank = os3d.Bank(shape, _orients(n), _params(n, L), device=self.device, stream=s)
             bank.ready = self.torch.cuda.Event()
             bank.ready.record(s)
         return bank
+
+    def consumer_stream(self, volume):
+        """The submitting thread's current stream: where the caller will use
+        the job's result."""
+        torch = self.torch
+        dev = volume.device if isinstance(volume, torch.Tensor) and volume.is_cuda else self.device
+        return torch.cuda.current_stream(dev)
+
+    def hand_over(self, result, stream):
+        """Mark the result's memory as used by the consumer's stream, so that
+        once the caller drops it the allocator waits for the work queued
+        there before giving the block to another launch."""
+        result.record_stream(stream)
 
     def free_bank(self, bank):
         bank.close()

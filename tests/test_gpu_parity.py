@@ -96,6 +96,13 @@ CASES = {
     # 33-48 stored rows: one 48-column sweep (up to 32 rows take a 32-column sweep)
     "rand40": lambda: ((10, 8, 12), _random_orients(40, 25), _oracle_params(10, 40),
                        inputs.tubes((10, 8, 12), 2, 1.2, 0.1, 0, 26)),
+    # the two non-power-of-two shapes of the serving workload (12 orientations
+    # to bound the oracle's time): radix 3 and 5 on the three-pass path, and
+    # a z axis of 160 under 128 x 128 planes on the plane path
+    "serve96x80x64": lambda: ((96, 80, 64), inputs.icosahedral_orientations(0), _oracle_params(24, 12),
+                              inputs.tubes((96, 80, 64), 12, (1.0, 3.0), 0.2, 0, 27)),
+    "serve160x128x128": lambda: ((160, 128, 128), inputs.icosahedral_orientations(0), _oracle_params(16, 12),
+                                 inputs.tubes((160, 128, 128), 12, (1.0, 3.0), 0.2, 0, 28)),
     # small N with radix-2 only and a long axis
     "long4x6x64": lambda: ((4, 6, 64), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                            inputs.tubes((4, 6, 64), 2, 1.0, 0.1, 0, 8)),
@@ -228,6 +235,16 @@ def test_reduced_precision_storage(torch_dev, fmt, bound, shape):
     Uq, sc = os3d.forward(f, gb, dtype=fmt)
     s = sc.cpu().numpy()
     assert np.all(np.log2(s) == np.round(np.log2(s)))
+    # the scales are the bound reading: the smallest power of two above
+    # (1/V) sum_k |psi_hat_i F| (times 2^-15 for fp16), up to one step where
+    # the bound lies within 1e-5 of a power of two
+    F = O.dft3(vol.astype(np.float64))
+    bounds = np.array([O.score_scale_bound(F, ob["psi_hat"][i]) for i in range(len(n))])
+    s_or = O.score_scales(bounds, fmt)
+    frac = np.array([np.frexp(b)[0] for b in bounds])
+    near = (frac > 1 - 1e-5) | (frac < 0.5 * (1 + 1e-5))
+    d_e = np.log2(s) - np.log2(s_or)
+    assert np.all((d_e == 0) | (near & (np.abs(d_e) == 1))), (s, s_or)
     U = os3d.unpack16(Uq, sc, fmt).cpu().numpy()
     Uo = O.forward(vol.astype(np.float64), ob)
     assert rel(U, Uo) < bound
@@ -274,6 +291,22 @@ def test_process_parity(case, phi, power):
     got = os3d.process(case["f"], case["gb"], phi, power).cpu().numpy()
     want = O.process(case["vol"].astype(np.float64), case["ob"], phi, power)
     assert rel(got, want) < TOL
+
+
+@pytest.mark.parametrize("power", [1.0, 0.5])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (12, 64, 64)], ids=["three_pass", "plane"])
+def test_process_soft_threshold_of_tiny_scores(torch_dev, shape, power):
+    """The soft threshold of Fig. 7 on a volume scaled by 1e-20: |U|^2 is
+    below the smallest normal float there, and the result must still match
+    the oracle (no NaN from the logarithm of a flushed square)."""
+    from paper_1505_07690_amd import os3d
+    n = inputs.icosahedral_orientations(0)
+    p = _oracle_params(8, 12)
+    vol = (inputs.tubes(shape, 2, 1.2, 0.1, 0, 29).astype(np.float64) * 1e-20).astype(np.float32)
+    ob, gb, f = _case(shape, n, p, vol)
+    got = os3d.process(f, gb, "soft_threshold", power).cpu().numpy()
+    assert np.all(np.isfinite(got))
+    assert rel(got, O.process(vol.astype(np.float64), ob, "soft_threshold", power)) < TOL
 
 
 def test_projection_parity(case):

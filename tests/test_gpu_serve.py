@@ -91,3 +91,26 @@ def test_tight_budget_serialises(torch):
     for v, o in zip(vols, outs):
         U, _ = os3d.forward(v, bank)
         assert torch.equal(o, os3d.reconstruct(U, bank))
+
+
+def test_result_consumed_on_the_callers_stream_survives_later_jobs(torch):
+    """A result is handed over to the stream it was submitted from: work the
+    caller queues there on it (behind a 50 ms spin) still reads the right
+    values after the caller drops the tensor and later jobs of the same
+    shape allocate their outputs."""
+    from paper_1505_07690_amd.serve import Server
+    shape = (64, 64, 64)
+    vols = [inputs.tubes_device(shape, 12, (1.0, 3.0), 0.2, 0, 300 + i) for i in range(5)]
+    torch.cuda.synchronize()
+    want = _alone(torch, vols[0], 42, 16, "reconstruct", "c64")
+    with Server(16 << 30, n_slots=2, max_batch=1) as s:
+        out = s.submit(vols[0], 42, 16).result(timeout=60)
+        consumed = torch.empty_like(want)
+        torch.cuda._sleep(120_000_000)  # bounded spin on the caller's stream
+        consumed.copy_(out)
+        del out
+        outs = [s.submit(v, 42, 16).result(timeout=60) for v in vols[1:]]
+        torch.cuda.synchronize()
+    assert torch.equal(consumed, want)
+    for v, o in zip(vols[1:], outs):
+        assert torch.equal(o, _alone(torch, v, 42, 16, "reconstruct", "c64"))

@@ -605,18 +605,52 @@ def test_line_vs_plate_detector():
 
 
 def test_quantisation_roundtrip_bounds():
-    """Per-orientation power-of-two scale with 16-bit storage: relative error
-    at the format's unit roundoff (2^-11 fp16, 2^-8 bf16)."""
+    """Per-orientation power-of-two scale with 16-bit storage, taken from the
+    bound (1/V) sum_k |psi_hat_i F| of max |U_i|: the bound holds, the scaled
+    values stay inside the format (below 1 for bf16, below 2^15 for fp16),
+    and the relative error is at the format's unit roundoff (2^-11 fp16,
+    2^-8 bf16)."""
     b, n, _ = _setup((8, 8, 8))
     f = np.random.default_rng(7).standard_normal((8, 8, 8))
     U = O.forward(f, b)
-    for fmt, bound in (("fp16", 2.0 ** -11), ("bf16", 2.0 ** -8)):
-        Q, s = O.quantize_scores(U, fmt)
+    F = O.dft3(f)
+    bounds = np.array([O.score_scale_bound(F, b["psi_hat"][i]) for i in range(len(n))])
+    umax = np.maximum(np.abs(U.real), np.abs(U.imag)).reshape(len(n), -1).max(axis=1)
+    assert np.all(umax <= bounds * (1 + 1e-12))
+    for fmt, bound, top in (("fp16", 2.0 ** -11, 2.0 ** 15), ("bf16", 2.0 ** -8, 1.0)):
+        s = O.score_scales(bounds, fmt)
         assert np.all(np.log2(s) == np.round(np.log2(s)))
+        assert np.all(bounds / s < top) and np.all(bounds / s >= top / 2)
+        Q = O.quantize_scores(U, fmt, s)
         assert rel(Q, U) < bound
+    # the smallest power of two above the bound; an exact power moves up
+    assert list(O.score_scales([0.75, 1.0, 3.0, 0.0], "bf16")) == [1.0, 2.0, 4.0, 1.0]
+    assert list(O.score_scales([0.75, 1.0], "fp16")) == [2.0 ** -15, 2.0 ** -14]
     # bf16 rounding is to nearest, ties to even
     x = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -9], dtype=np.float32)
     assert list(O.os3d_oracle._bf16_round(x)) == [1.0, 1 + 2 ** -6, 1.0]
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (12, 10, 16), (9, 8, 10)])
+def test_streamed_bank_quantities_equal_the_full_grid_ones(shape):
+    """kappa over the band, M at sampled indices and a whole bank row
+    computed without the full grid (for 256^3) equal build_bank's."""
+    p = O.WaveletParams(L=8, s_theta=1.31)
+    n = inputs.icosahedral_orientations(1)
+    b = O.build_bank(shape, n, p)
+    a = b["a"]
+    k = O.band_kappa_streamed(shape, n, a, p, chunk=97)
+    assert abs(k - b["kappa"]) < 1e-13 * b["kappa"]
+    idx = np.random.default_rng(3).integers(0, int(np.prod(shape)), 300)
+    assert np.max(np.abs(O.M_at(shape, idx, n, a, p, b["kappa"], chunk=64) - b["M"].ravel()[idx])) < 1e-13
+    for i in (0, 17):
+        assert np.max(np.abs(O.bank_row(shape, n[i], a, p, b["kappa"], slab=5) - b["psi_hat"][i])) < 1e-14
+    wz, wy, wx, nyq = O.freq_at(shape, idx)
+    gz, gy, gx, gq = O.freq_grid(shape)
+    kz, r = np.divmod(idx, shape[1] * shape[2])
+    ky, kx = np.divmod(r, shape[2])
+    assert np.array_equal(wz, gz[kz, 0, 0]) and np.array_equal(wy, gy[0, ky, 0]) and np.array_equal(wx, gx[0, 0, kx])
+    assert np.array_equal(nyq, gq[kz, ky, kx])
 
 
 # ------------------------------------------- approximate reconstruction ----

@@ -29,10 +29,11 @@ class FakeHandle:
 
 
 class FakeExecutor:
-    def __init__(self, n_slots, run_s=0.02, fail_keys=()):
+    def __init__(self, n_slots, run_s=0.02, fail_keys=(), build_s=None):
         self.n_slots = n_slots
         self.run_s = run_s
         self.fail_keys = set(fail_keys)
+        self.build_s = dict(build_s or {})
         self.lock = threading.Lock()
         self.active = 0
         self.max_active = 0
@@ -49,7 +50,8 @@ class FakeExecutor:
             raise ValueError("unsupported orientation count")
         return int(np.prod(shape)) * n * 2
 
-    def build_bank(self, key, slot):
+    def build_bank(self, key):
+        time.sleep(self.build_s.get(key, 0.0))
         if key in self.fail_keys:
             raise RuntimeError("bank build failed")
         self.built.append(key)
@@ -299,3 +301,25 @@ def test_waits_for_running_jobs_instead_of_evicting():
         st = s.stats()
     assert st["bank_evictions"] == 0 and ex.freed == []
     assert st["ok"] == 3 and st["errors"] == {}
+
+
+def test_a_slow_bank_build_does_not_stall_other_keys():
+    """A bank is built on a thread of its own: while one key's bank takes
+    0.5 s, jobs of a key whose bank is cached are still reaped and
+    admitted."""
+    slow = ((16, 16, 16), 162, 24)
+    ex = FakeExecutor(2, run_s=0.01, build_s={slow: 0.5})
+    with Server(1 << 30, n_slots=2, max_batch=1, executor=ex) as s:
+        s.submit(vol((8, 8, 8), 0), 42, 16).result(timeout=5)  # caches the fast key's bank
+        t0 = time.perf_counter()
+        fs = s.submit(vol((16, 16, 16), 1), 162, 24)
+        time.sleep(0.02)
+        fast = [s.submit(vol((8, 8, 8), 2 + i), 42, 16) for i in range(5)]
+        for f in fast:
+            f.result(timeout=5)
+        t_fast = time.perf_counter() - t0
+        assert not fs.done()
+        fs.result(timeout=5)
+        st = s.stats()
+    assert t_fast < 0.3, t_fast
+    assert st["ok"] == 7 and st["bank_builds"] == 2 and st["bank_build_ms_max"] >= 500
