@@ -150,7 +150,7 @@ def test_headline_bank_rows_scores_and_scales(hl):
             uq = os3d.unpack16(Uq[i:i + 1], sc[i:i + 1], fmt)[0].cpu().numpy()
             num[fmt] += float(np.sum(np.abs(uq - Uo) ** 2))
             umax = max(np.abs(uq.real).max(), np.abs(uq.imag).max())
-            peak[fmt] = max(peak[fmt], umax / (s_gpu * top))
+            peak[fmt] = max(peak[fmt], float(umax) / (s_gpu * top))
             assert umax / s_gpu < top
         del Uo
     errs = {m: math.sqrt(num[m] / den) for m in num}
@@ -187,4 +187,4 @@ def test_headline_reconstruction(hl):
         errs[mode] = e_uni
         hl["report"].setdefault("rec_rel_l2_near_nyquist", {})[mode] = e_near
     hl["report"]["rec_rel_l2"] = errs
-    print("PRECISION " + json.dumps(hl["report"]), flush=True)
+    print("PRECISION " + json.dumps(hl["report"], default=float), flush=True)
