@@ -31,7 +31,8 @@ struct PassArgs {
   const float* src_r;
   const float2* src_c;
   long long src_stride;  // per pair (elements)
-  const float* psi;      // bank rows
+  const float* psi;      // bank rows (without kappa)
+  float kappa;           // the bank's normaliser: LM_MULBANK multiplies by kappa psi, LM_DIVM by kappa
   int rows[kMaxBatch];
   int oa[kMaxBatch], ob[kMaxBatch];  // stored member, partner (-1 if none)
   const void* U;
@@ -128,7 +129,7 @@ __device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long 
   } else if constexpr (LM == LM_C) {
     return a.src_c[j * a.src_stride + g];
   } else if constexpr (LM == LM_MULBANK) {
-    const float p = a.psi[(long long)a.rows[j] * a.V + g];
+    const float p = a.psi[(long long)a.rows[j] * a.V + g] * a.kappa;
     const float2 v = cscale(a.src_c[g], p);
     if (a.partial) asum += sqrtf(v.x * v.x + v.y * v.y);  // scale bound of 16-bit storage only
     return v;
@@ -142,9 +143,8 @@ __device__ __forceinline__ float2 load_elem(const PassArgs& a, int j, long long 
     }
     return v;
   } else {  // LM_DIVM
-    float2 v = a.src_c[g];
-    if (a.divide) v = cscale(v, 1.f / fmaxf(a.M[g], a.eps));
-    return v;
+    const float2 v = a.src_c[g];
+    return cscale(v, a.divide ? a.kappa / fmaxf(a.M[g], a.eps) : a.kappa);
   }
 }
 
@@ -220,7 +220,7 @@ __device__ __forceinline__ void load_k(const PassArgs& a, int j, long long g0, l
 #pragma unroll
     for (int r = 0; r < K; ++r) v[r] = a.src_c[g0 + r * d];
 #pragma unroll
-    for (int r = 0; r < K; ++r) v[r] = cscale(v[r], ps[r]);
+    for (int r = 0; r < K; ++r) v[r] = cscale(v[r], ps[r] * a.kappa);
     if (a.partial) {  // scale bound of 16-bit storage only
 #pragma unroll
       for (int r = 0; r < K; ++r) asum += sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
@@ -251,7 +251,10 @@ __device__ __forceinline__ void load_k(const PassArgs& a, int j, long long g0, l
 #pragma unroll
       for (int r = 0; r < K; ++r) m[r] = a.M[g0 + r * d];
 #pragma unroll
-      for (int r = 0; r < K; ++r) v[r] = cscale(v[r], 1.f / fmaxf(m[r], a.eps));
+      for (int r = 0; r < K; ++r) v[r] = cscale(v[r], a.kappa / fmaxf(m[r], a.eps));
+    } else {
+#pragma unroll
+      for (int r = 0; r < K; ++r) v[r] = cscale(v[r], a.kappa);
     }
   }
 }

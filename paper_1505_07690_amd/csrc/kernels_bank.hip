@@ -14,7 +14,11 @@
 // (prefetched during the recursion and staged in LDS).  The epilogue
 // multiplies by the FP64 radial window g(rho) (Eq. 10), applies the Nyquist
 // and DC rules, writes the bank rows and accumulates sum_i psi_i^2 (Eq. 9)
-// in FP64 with a fixed-order cross-lane tree.
+// and sum_i psi_i in FP64 with a fixed-order cross-lane tree; the
+// workgroup's sums of both over the normalisation band go to one partial
+// record per workgroup.  The rows are stored without the normaliser kappa
+// (known only once every partial is in): the transforms apply kappa as a
+// scalar where they multiply by the bank.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -48,6 +52,7 @@ struct BankArgs {
   const int* koff;   // chunk offsets [L+1] | padded lengths [L+1]
   float* psi;        // [n_rows][V]
   double* Mh;        // [V]
+  double* part;      // [gridDim.x][3]: band sums of Mh and of sum_i psi_i, band count
 };
 
 __device__ inline double omega_of(int k, int n) {
@@ -79,8 +84,9 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
   extern __shared__ float Ybuf[];  // [qpad_max][kYStride], then cos and sin steering rows [2][qpad_max][cols]
   __shared__ double gsh[kBankPts];
   __shared__ double Msh[kBankPts];
+  __shared__ double Ash[kBankPts];
   __shared__ float crsh[kBankPts], cish[kBankPts];
-  __shared__ int dcsh[kBankPts];
+  __shared__ int dcsh[kBankPts], bandsh[kBankPts];
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long long p0 = (long long)blockIdx.x * kBankPts;
@@ -96,6 +102,7 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
   // this thread's frequency point
   double ux = 0.0, uy = 0.0, uz = 1.0, g = 0.0;
   int dc = 0;
+  bool band = false;  // the normalisation band: 0 < rho <= rho_N / 2, no Nyquist plane
   if (valid) {
     int kz, ky, kx;
     pos_to_k(a.layout, p, a.Nz, a.Ny, a.Nx, kz, ky, kx);
@@ -111,10 +118,14 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
     }
     bool nyq = is_nyquist(kx, a.Nx) || is_nyquist(ky, a.Ny) || is_nyquist(kz, a.Nz);
     g = nyq ? 0.0 : radial_g(r2, a.t_inv, a.taylor_N);
+    const double hn = 0.5 * 3.14159265358979323846;
+    band = !nyq && r2 > 0.0 && r2 <= hn * hn;
   }
   gsh[tid] = g;
   dcsh[tid] = dc;
+  bandsh[tid] = band ? 1 : 0;
   Msh[tid] = 0.0;
+  double asum = 0.0;  // this lane's share of the band sum of sum_i psi_raw
 
   constexpr int kCols = 16 * CB;  // columns per sweep
   // NS sweeps of kCols columns share each order's recursion: one FP64 pass of
@@ -230,7 +241,8 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
       __syncthreads();
     }
 
-    // epilogue: psi_raw = g * h (DC: isotropic), bank rows, FP64 sum of squares
+    // epilogue: psi_raw = g * h (DC: isotropic), bank rows, FP64 sums of
+    // squares and of values
 #pragma unroll
     for (int w = 0; w < NS; ++w) {
       const int cs = c0 + w * kCols;
@@ -255,7 +267,10 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
             double h = dcsh[pt] ? a.dc_value : (double)acc[w][r][c][i];
             float v = (float)(gsh[pt] * h);
             if (colok && gp < a.V) a.psi[(long long)col * a.V + gp] = v;
-            if (colok) mh[r][i] += (double)v * (double)v;
+            if (colok) {
+              mh[r][i] += (double)v * (double)v;
+              if (bandsh[pt]) asum += (double)v;
+            }
           }
         }
       }
@@ -275,7 +290,30 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
     }
   }
   __syncthreads();
-  if (valid) a.Mh[p] = Msh[tid];
+  const double mt = Msh[tid];
+  if (valid) a.Mh[p] = mt;
+  // the workgroup's band sums, by a fixed tree (deterministic); Msh and
+  // Ash are reused as the tree's buffers
+  double cnt = band ? 1.0 : 0.0;
+  double ms = band ? mt : 0.0, as = asum;
+  __syncthreads();
+  Msh[tid] = ms;
+  Ash[tid] = as;
+  gsh[tid] = cnt;
+  __syncthreads();
+  for (int w = kBankPts / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      Msh[tid] += Msh[tid + w];
+      Ash[tid] += Ash[tid + w];
+      gsh[tid] += gsh[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.part[3 * (long long)blockIdx.x] = Msh[0];
+    a.part[3 * (long long)blockIdx.x + 1] = Ash[0];
+    a.part[3 * (long long)blockIdx.x + 2] = gsh[0];
+  }
 }
 
 // S: k -> -k mod N on every axis, on storage positions.
@@ -285,109 +323,53 @@ __device__ inline long long mirror_index(int layout, long long p, int Nz, int Ny
   return k_to_pos(layout, (Nz - kz) % Nz, (Ny - ky) % Ny, (Nx - kx) % Nx, Ny, Nx);
 }
 
-// Partial sums over the band (rho <= rho_N / 2, no Nyquist plane, k != 0) of
-// the un-normalised M0[k] = Mh[k] (+ Mh[-k] for antipodal pairs).
-__global__ __launch_bounds__(256) void k_kappa_partial(const double* Mh, int paired, int layout, int Nz, int Ny,
-                                                       int Nx, long long V, double* part) {
-  __shared__ double ssum[256];
-  __shared__ double scnt[256];
+// kappa and the approximate-reconstruction normaliser from the synthesis
+// workgroups' band partials, summed in a fixed order (deterministic).  The
+// band is symmetric under k -> -k, so for an antipodal set the partner's
+// terms (the stored row read at -k) add the same band sums again:
+//   kappa = (mean over the band of M0)^(-1/2), M0[k] = Mh[k] (+ Mh[-k]);
+//   S = kappa x (mean over the band of sum over every orientation of psi_raw).
+// out[0] = kappa, out[1] = S.
+__global__ __launch_bounds__(1024) void k_bank_reduce(const double* part, long long nparts, int paired, double* out) {
+  __shared__ double sm[1024], sa[1024], sc[1024];
   const int tid = threadIdx.x;
-  const long long chunk = (V + gridDim.x - 1) / gridDim.x;
-  const long long b = (long long)blockIdx.x * chunk, e = min(V, b + chunk);
-  double s = 0.0, cnt = 0.0;
-  const double half = 0.5 * 3.14159265358979323846;
-  for (long long p = b + tid; p < e; p += 256) {
-    int kz, ky, kx;
-    pos_to_k(layout, p, Nz, Ny, Nx, kz, ky, kx);
-    if (is_nyquist(kx, Nx) || is_nyquist(ky, Ny) || is_nyquist(kz, Nz)) continue;
-    double wx = omega_of(kx, Nx), wy = omega_of(ky, Ny), wz = omega_of(kz, Nz);
-    double rho = sqrt(wx * wx + wy * wy + wz * wz);
-    if (rho > 0.0 && rho <= half) {
-      double m0 = Mh[p] + (paired ? Mh[mirror_index(layout, p, Nz, Ny, Nx)] : 0.0);
-      s += m0;
-      cnt += 1.0;
-    }
+  double m = 0.0, av = 0.0, c = 0.0;
+  for (long long i = tid; i < nparts; i += 1024) {
+    m += part[3 * i];
+    av += part[3 * i + 1];
+    c += part[3 * i + 2];
   }
-  ssum[tid] = s;
-  scnt[tid] = cnt;
+  sm[tid] = m;
+  sa[tid] = av;
+  sc[tid] = c;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if (tid < w) {
-      ssum[tid] += ssum[tid + w];
-      scnt[tid] += scnt[tid + w];
+      sm[tid] += sm[tid + w];
+      sa[tid] += sa[tid + w];
+      sc[tid] += sc[tid + w];
     }
     __syncthreads();
   }
   if (tid == 0) {
-    part[2 * blockIdx.x] = ssum[0];
-    part[2 * blockIdx.x + 1] = scnt[0];
+    const double f = paired ? 2.0 : 1.0;
+    const double cnt = sc[0];
+    const double mean_m = f * sm[0] / cnt;
+    const double kappa = (cnt > 0.0 && mean_m > 0.0) ? 1.0 / sqrt(mean_m) : 1.0;
+    out[0] = kappa;
+    out[1] = (cnt > 0.0) ? kappa * f * sa[0] / cnt : 1.0;
   }
 }
 
-__global__ void k_kappa_final(double* part, int nparts) {
-  if (threadIdx.x == 0) {
-    double s = 0.0, c = 0.0;
-    for (int i = 0; i < nparts; ++i) {
-      s += part[2 * i];
-      c += part[2 * i + 1];
-    }
-    part[2 * nparts] = (c > 0.0 && s > 0.0) ? 1.0 / sqrt(s / c) : 1.0;
-  }
-}
-
-// Partial sums over the band of sum_i psi_hat_i[k] (all orientations: a
-// stored row counts at k and, for an antipodal pair, at -k): the normaliser
-// of the approximate reconstruction of Eq. (6).
-__global__ __launch_bounds__(256) void k_approx_partial(const float* psi, int n_rows, int paired, int layout, int Nz,
-                                                        int Ny, int Nx, long long V, double* part) {
-  __shared__ double ssum[256];
-  __shared__ double scnt[256];
-  const int tid = threadIdx.x;
-  const long long chunk = (V + gridDim.x - 1) / gridDim.x;
-  const long long b = (long long)blockIdx.x * chunk, e = min(V, b + chunk);
-  double s = 0.0, cnt = 0.0;
-  const double half = 0.5 * 3.14159265358979323846;
-  for (long long p = b + tid; p < e; p += 256) {
-    int kz, ky, kx;
-    pos_to_k(layout, p, Nz, Ny, Nx, kz, ky, kx);
-    if (is_nyquist(kx, Nx) || is_nyquist(ky, Ny) || is_nyquist(kz, Nz)) continue;
-    double wx = omega_of(kx, Nx), wy = omega_of(ky, Ny), wz = omega_of(kz, Nz);
-    double rho = sqrt(wx * wx + wy * wy + wz * wz);
-    if (rho > 0.0 && rho <= half) {
-      const long long q = paired ? mirror_index(layout, p, Nz, Ny, Nx) : p;
-      double t = 0.0;
-      for (int r = 0; r < n_rows; ++r) {
-        t += (double)psi[(long long)r * V + p];
-        if (paired) t += (double)psi[(long long)r * V + q];
-      }
-      s += t;
-      cnt += 1.0;
-    }
-  }
-  ssum[tid] = s;
-  scnt[tid] = cnt;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) {
-      ssum[tid] += ssum[tid + w];
-      scnt[tid] += scnt[tid + w];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    part[2 * blockIdx.x] = ssum[0];
-    part[2 * blockIdx.x + 1] = scnt[0];
-  }
-}
-
-__global__ void k_approx_final(double* part, int nparts) {
-  if (threadIdx.x == 0) {
-    double s = 0.0, c = 0.0;
-    for (int i = 0; i < nparts; ++i) {
-      s += part[2 * i];
-      c += part[2 * i + 1];
-    }
-    part[2 * nparts + 1] = (c > 0.0) ? s / c : 1.0;
+// M = kappa^2 M0 (Eq. 9 with its constants in kappa), M0[k] = Mh[k] (+ Mh[-k]
+// for an antipodal set: the partner's row is the stored row at -k).
+__global__ __launch_bounds__(256) void k_M_finalize(const double* Mh, float* M, int paired, int layout, int Nz,
+                                                    int Ny, int Nx, long long V, const double* kappa_p) {
+  const double kappa = *kappa_p;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < V; p += stride) {
+    const double m0 = Mh[p] + (paired ? Mh[mirror_index(layout, p, Nz, Ny, Nx)] : 0.0);
+    M[p] = (float)(kappa * kappa * m0);
   }
 }
 
@@ -447,24 +429,10 @@ __global__ __launch_bounds__(256) void k_approx_reconstruct(const void* U, const
 }
 
 
-// psi *= kappa; M = kappa^2 M0.
-__global__ __launch_bounds__(256) void k_bank_finalize(float* psi, int n_rows, double* Mh, float* M, int paired,
-                                                       int layout, int Nz, int Ny, int Nx, long long V,
-                                                       const double* kappa_p) {
-  const double kappa = *kappa_p;
-  const float kf = (float)kappa;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < V; p += stride) {
-    double m0 = Mh[p] + (paired ? Mh[mirror_index(layout, p, Nz, Ny, Nx)] : 0.0);
-    M[p] = (float)(kappa * kappa * m0);
-    for (int r = 0; r < n_rows; ++r) psi[(long long)r * V + p] *= kf;
-  }
-}
-
-// Natural-order export: out[k] = row[pos(k)] (or row[pos(-k)] for the
-// second member of an antipodal pair).
+// Natural-order export: out[k] = scale x row[pos(k)] (or row[pos(-k)] for
+// the second member of an antipodal pair).
 __global__ __launch_bounds__(256) void k_export(const float* row, int mirrored, int layout, int Nz, int Ny, int Nx,
-                                                long long V, float* out) {
+                                                long long V, float scale, float* out) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < V; p += stride) {
     int kx = (int)(p % Nx);
@@ -475,7 +443,7 @@ __global__ __launch_bounds__(256) void k_export(const float* row, int mirrored, 
       ky = (Ny - ky) % Ny;
       kz = (Nz - kz) % Nz;
     }
-    out[p] = row[k_to_pos(layout, kz, ky, kx, Ny, Nx)];
+    out[p] = scale * row[k_to_pos(layout, kz, ky, kx, Ny, Nx)];
   }
 }
 
@@ -509,6 +477,7 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   a.koff = (const int*)(b->d.tab + nn + 2 * nn * nn);
   a.psi = b->d.psi;
   a.Mh = b->d.Mh;
+  a.part = b->d.part;
   a.dc_value = b->dc_value;
   // LDS rows per chunk: the L + 1 - m values Q_l^m, padded to 4 (largest at m = 0)
   const int maxpad = (nn + 3) / 4 * 4;
@@ -536,23 +505,15 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   prof_stop(tok, st, PROF_BANK, 0.0, 2.0 * (double)b->V * (double)(nn * nn) * (double)b->n_unique);
   int rc = check_launch("k_bank_synth");
   if (rc) return rc;
-  const int nparts = 1024;
-  launch_k(k_kappa_partial, dim3(nparts), dim3(256), 0, st, b->d.Mh, b->paired, b->layout, a.Nz, a.Ny,
-                     a.Nx, a.V, b->d.part);
-  if ((rc = check_launch("k_kappa_partial"))) return rc;
-  launch_k(k_kappa_final, dim3(1), dim3(64), 0, st, b->d.part, nparts);
-  if ((rc = check_launch("k_kappa_final"))) return rc;
+  launch_k(k_bank_reduce, dim3(1), dim3(1024), 0, st, (const double*)b->d.part, nblk, b->paired,
+           b->d.part + 3 * nblk);
+  if ((rc = check_launch("k_bank_reduce"))) return rc;
   const unsigned fin_blocks = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
-  launch_k(k_bank_finalize, dim3(fin_blocks), dim3(256), 0, st, b->d.psi, b->n_unique, b->d.Mh, b->d.M,
-                     b->paired, b->layout, a.Nz, a.Ny, a.Nx, a.V, b->d.part + 2 * nparts);
-  if ((rc = check_launch("k_bank_finalize"))) return rc;
-  launch_k(k_approx_partial, dim3(nparts), dim3(256), 0, st, b->d.psi, b->n_unique, b->paired, b->layout,
-                     a.Nz, a.Ny, a.Nx, a.V, b->d.part);
-  if ((rc = check_launch("k_approx_partial"))) return rc;
-  launch_k(k_approx_final, dim3(1), dim3(64), 0, st, b->d.part, nparts);
-  if ((rc = check_launch("k_approx_final"))) return rc;
+  launch_k(k_M_finalize, dim3(fin_blocks), dim3(256), 0, st, (const double*)b->d.Mh, b->d.M, b->paired, b->layout,
+           a.Nz, a.Ny, a.Nx, a.V, (const double*)(b->d.part + 3 * nblk));
+  if ((rc = check_launch("k_M_finalize"))) return rc;
   double kn[2] = {0.0, 0.0};
-  if (hipMemcpyAsync(kn, b->d.part + 2 * nparts, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  if (hipMemcpyAsync(kn, b->d.part + 3 * nblk, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
     set_error("os3d_build_bank: reading kappa failed");
     return OS3D_EDEVICE;
@@ -608,14 +569,14 @@ int launch_export_psi(const os3d_bank* b, int i, float* out, void* stream) {
   const float* row = b->d.psi + (long long)b->row_of[i] * b->V;
   const unsigned nb = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
   launch_k(k_export, dim3(nb), dim3(256), 0, (hipStream_t)stream, row, b->conj_of[i], b->layout,
-                     (int)b->dims[0], (int)b->dims[1], (int)b->dims[2], b->V, out);
+                     (int)b->dims[0], (int)b->dims[1], (int)b->dims[2], b->V, (float)b->kappa, out);
   return check_launch("k_export");
 }
 
 int launch_export_M(const os3d_bank* b, float* out, void* stream) {
   const unsigned nb = (unsigned)std::min<long long>((b->V + 255) / 256, 8192);
   launch_k(k_export, dim3(nb), dim3(256), 0, (hipStream_t)stream, b->d.M, 0, b->layout, (int)b->dims[0],
-                     (int)b->dims[1], (int)b->dims[2], b->V, out);
+                     (int)b->dims[1], (int)b->dims[2], b->V, 1.f, out);
   return check_launch("k_export");
 }
 

@@ -615,6 +615,7 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
       }
       z.src_c = F;
       z.psi = b->d.psi;
+      z.kappa = (float)b->kappa;
       z.dst_c = T;
       z.dst_stride = V;
       const bool quant = dtype != OS3D_C64;
@@ -724,6 +725,7 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
       z.src_c = T;
       z.src_stride = V;
       z.psi = b->d.psi;
+      z.kappa = (float)b->kappa;
       z.dst_c = X;
       z.accumulate = (r0 > 0) ? 1 : 0;
       if ((rc = run_pass<LM_C, SM_ACCUM>(kProfRecLast, 0.0, z, 1, st))) return rc;
@@ -735,6 +737,7 @@ int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* sca
     z.nb = 1;
     z.src_c = X;
     z.M = b->d.M;
+    z.kappa = (float)b->kappa;
     z.eps = (float)b->params.eps;
     z.divide = divide_M ? 1 : 0;
     z.dst_c = X;
@@ -800,6 +803,7 @@ int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, 
       }
       z.src_c = F;
       z.psi = b->d.psi;
+      z.kappa = (float)b->kappa;
       z.dst_c = T;
       z.dst_stride = V;
       if ((rc = run_pass<LM_MULBANK, SM_C>(kProfFwdFirst, 0.0, z, nb, st))) return rc;
@@ -873,6 +877,7 @@ int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, 
     z.nb = 1;
     z.src_c = X;
     z.M = b->d.M;
+    z.kappa = (float)b->kappa;
     z.eps = (float)b->params.eps;
     z.divide = 1;
     z.dst_c = X;

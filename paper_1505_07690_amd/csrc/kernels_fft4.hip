@@ -73,9 +73,9 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
   load_twiddles(a, twl);
   const long long base = (long long)tile << 14;
   float2 spec[16];
-  if constexpr (LM == LM_MULBANK) {
+  if constexpr (LM == LM_MULBANK) {  // F times the bank's normaliser, once for the launch
 #pragma unroll
-    for (int r = 0; r < 16; ++r) spec[r] = a.src_c[base + t + r * 1024];
+    for (int r = 0; r < 16; ++r) spec[r] = cscale(a.src_c[base + t + r * 1024], a.kappa);
   } else {
     float unused = 0.f;
     load_k<LM, OS3D_C64, 16>(a, 0, base + t, 1024, spec, unused);
@@ -400,6 +400,7 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
       }
       z.src_c = F;
       z.psi = b->d.psi;
+      z.kappa = (float)b->kappa;
       z.dst_c = T;
       z.dst_stride = V;
       z.partial = quant ? partial : nullptr;
@@ -482,6 +483,7 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
       z.src_c = T;
       z.src_stride = V;
       z.psi = b->d.psi;
+      z.kappa = (float)b->kappa;
       z.dst_c = X;
       z.accumulate = (r0 > 0) ? 1 : 0;
       OS3D_LAUNCH4((k4_fwd_phi<SM_ACCUM>), kProfRecLast, 0.0, z, 1);
@@ -489,6 +491,7 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
     PassArgs z = base_args(b, 1.f);
     z.src_c = X;
     z.M = b->d.M;
+    z.kappa = (float)b->kappa;
     z.eps = (float)b->params.eps;
     z.divide = divide_M ? 1 : 0;
     z.dst_c = T;
@@ -539,6 +542,7 @@ int process4(const os3d_bank* b, const float* f, int batch, int phi_kind, float 
       }
       z.src_c = F;
       z.psi = b->d.psi;
+      z.kappa = (float)b->kappa;
       z.dst_c = T;
       z.dst_stride = V;
       OS3D_LAUNCH4((k4_inv_phi<LM_MULBANK>), kProfFwdFirst, 0.0, z, 1);
@@ -570,6 +574,7 @@ int process4(const os3d_bank* b, const float* f, int batch, int phi_kind, float 
     PassArgs z = base_args(b, 1.f);
     z.src_c = X;
     z.M = b->d.M;
+    z.kappa = (float)b->kappa;
     z.eps = (float)b->params.eps;
     z.divide = 1;
     z.dst_c = T;

@@ -109,8 +109,8 @@ static BankLayout layout(const int64_t dims[3], int n_unique, int L) {
   o = align256(o + (size_t)kl.K * Npad * sizeof(float));
   b.tab = o;
   o = align256(o + (size_t)(nn + 2 * nn * nn + nn) * sizeof(double));
-  b.part = o;
-  o = align256(o + (2 * 1024 + 2) * sizeof(double));
+  b.part = o;  // band partials of the synthesis workgroups (3 each), then kappa and S
+  o = align256(o + (3 * ((V + 255) / 256) + 2) * sizeof(double));
   for (int d = 0; d < 3; ++d) {
     b.tw[d] = o;
     o = align256(o + (size_t)dims[d] * 2 * sizeof(float));

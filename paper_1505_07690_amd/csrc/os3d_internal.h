@@ -69,12 +69,12 @@ struct AxisPlan {
 };
 
 struct DevPtrs {
-  float* psi;      // [n_unique][V] float32, unnormalised during build then scaled by kappa
+  float* psi;      // [n_unique][V] float32 g h without kappa (the transforms apply kappa)
   float* M;        // [V]
   double* Mh;      // [V] FP64 sum over stored rows of raw psi^2 (build scratch)
   float* S;        // [K][Npad] steering matrix in K-layout
   double* tab;     // recursion tables: qmm[L+1], alm[(L+1)^2], blm[(L+1)^2], sqrt(2m+3)[L+1]
-  double* part;    // kappa partial sums
+  double* part;    // band partials of the synthesis, then kappa and S
   float* tw[3];    // twiddles exp(-2 pi i j / N_d), j < N_d, per axis (z, y, x)
 };
 
