@@ -202,6 +202,22 @@ os3d_status os3d_reconstruct_approx(const os3d_bank* bank, const void* U, int32_
 os3d_status os3d_process(const os3d_bank* bank, const float* f, int32_t batch, int32_t phi, double phi_power,
                          float* f_out, void* ws, size_t ws_bytes, void* stream);
 
+/* os3d_reconstruct without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that
+ * must not call hipMalloc): the library's own static device scratch array
+ * (64 MiB, held on every device the library runs on until the process ends)
+ * takes the place of the workspace, and the call allocates nothing.  It
+ * holds the orientation sum and the intermediates of as many orientation
+ * pairs per launch as fit (at least one): volumes up to 2^22 voxels, e.g.
+ * 128^3 or 160 x 128 x 128; a larger volume returns OS3D_ENOMEM before any
+ * work is enqueued.  Every call on one device shares that device's scratch:
+ * calls that overlap on one device (different streams or threads without
+ * ordering between them) race and give wrong results.  The result equals
+ * os3d_reconstruct's up to the summation order of the orientation pairs
+ * (FP32 rounding).  Other arguments and errors as for os3d_reconstruct. */
+os3d_status os3d_reconstruct_noalloc(const os3d_bank* bank, const void* U, int32_t dtype, const float* scales,
+                                     int32_t batch, float* f_out, void* stream);
+
 /* Per-kernel timing (not a method step: measurement support).  While
  * enabled, a timed launch carries two HIP events that the runtime stamps
  * with the kernel's start and end on its launch stream, and the algorithmic

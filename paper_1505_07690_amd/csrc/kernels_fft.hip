@@ -672,13 +672,23 @@ int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int d
   return OS3D_OK;
 }
 
+int reduce_pair_batch(const os3d_bank* b, long long ws_bytes) {
+  // X and one intermediate volume per pair of a launch
+  const long long vol = b->V * (long long)sizeof(float2);
+  const int fit = (int)std::min<long long>(kMaxBatch, ws_bytes / vol - 1);
+  if (fit < 1) return 0;
+  int nb = std::min(pair_batch(b), fit);
+  const int launches = (b->n_unique + nb - 1) / nb;
+  return (b->n_unique + launches - 1) / launches;
+}
+
 int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out,
-                  void* ws, bool divide_M, void* stream) {
+                  void* ws, bool divide_M, void* stream, int nb_limit) {
+  const int nbmax = nb_limit > 0 ? nb_limit : pair_batch(b);
   if (b->layout == kLayoutFour256)
-    return reduce4(b, U, dtype, scales, batch, f_out, ws, divide_M, pair_batch(b), stream);
+    return reduce4(b, U, dtype, scales, batch, f_out, ws, divide_M, nbmax, stream);
   hipStream_t st = (hipStream_t)stream;
   const long long V = b->V;
-  const int nbmax = pair_batch(b);
   float2* X = (float2*)ws;
   float2* T = X + V;
   const size_t ubytes = (dtype == OS3D_C64) ? 8 : 4;

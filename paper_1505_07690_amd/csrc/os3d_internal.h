@@ -110,8 +110,13 @@ namespace os3d {
 int launch_build_bank(os3d_bank* b, void* stream);
 int launch_forward(const os3d_bank* b, const float* f, int batch, void* U, int dtype, float* scales, void* ws,
                    void* stream);
+// nb_limit > 0 caps the orientation pairs per launch (the workspace then
+// needs X and nb_limit intermediate volumes); 0 takes the default batch.
 int launch_reduce(const os3d_bank* b, const void* U, int dtype, const float* scales, int batch, float* f_out,
-                  void* ws, bool divide_M, void* stream);
+                  void* ws, bool divide_M, void* stream, int nb_limit = 0);
+// Largest even pair batch whose reduction intermediates (X and one volume
+// per pair) fit ws_bytes; 0 if not even one pair fits.
+int reduce_pair_batch(const os3d_bank* b, long long ws_bytes);
 int launch_export_psi(const os3d_bank* b, int i, float* out, void* stream);
 int launch_process(const os3d_bank* b, const float* f, int batch, int phi_kind, float phi_p, float* f_out, void* ws,
                    void* stream);

@@ -58,6 +58,8 @@ _SIGS = {
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "os3d_reconstruct": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "os3d_reconstruct_noalloc": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                 ctypes.c_void_p, ctypes.c_void_p],
     "os3d_reconstruct_approx": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                 ctypes.c_void_p, ctypes.c_void_p],
     "os3d_process": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
@@ -336,6 +338,20 @@ def adjoint(U, bank, scales=None, dtype="c64", ws=None, out=None, stream=None):
 def reconstruct(U, bank, scales=None, dtype="c64", ws=None, out=None, stream=None):
     """Stabilised exact reconstruction, Eq. (8) with max(M, eps)."""
     return _reduce(lib().os3d_reconstruct, U, bank, scales, dtype, ws, out, stream)
+
+
+def reconstruct_noalloc(U, bank, scales=None, dtype="c64", out=None, stream=None):
+    """os3d_reconstruct with the library's static device scratch instead of a
+    workspace (no device allocation inside the call; volumes up to 2^22
+    voxels; calls that overlap on one device race)."""
+    Ub, code = _scores(U, bank, dtype)
+    B = Ub.shape[0]
+    out = _volume_out(out, B, bank)
+    sc = _scales_arg(scales, B, bank, code)
+    _check(lib().os3d_reconstruct_noalloc(bank.handle, ctypes.c_void_p(Ub.data_ptr()), code,
+                                          ctypes.c_void_p(sc.data_ptr() if sc is not None else 0), B,
+                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out if U.dim() == 5 or out.dim() == 3 else out[0]
 
 
 def reconstruct_approx(U, bank, scales=None, dtype="c64", out=None, stream=None):
