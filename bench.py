@@ -56,6 +56,9 @@ def parse():
                          "(Eq. 23, soft threshold p = 1.5) fused so that U never reaches memory")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stream-ceiling", action="store_true", help="skip the device copy/read/write rates")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the 16-bit, differentiation and serving forms")
+    ap.add_argument("--extra-requests", type=int, default=200, help="requests of the short serving runs")
     ap.add_argument("--cpu-orients", type=int, default=None,
                     help="orientations in the oracle's timed sample (default: 12 of 162 at 256^3, all 42 at 128^3, "
                          "about 10 s of host work each)")
@@ -123,10 +126,11 @@ def load_traffic(kernel, digest):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(workload, n_sample):
+def cpu_baseline(workload, n_sample, keep=None):
     """The FP64 oracle, as it stands, on a bounded sample of the workload:
     the same volume, n_sample orientations of the same set (bank built
-    untimed), timed forward + reconstruct."""
+    untimed), timed forward + reconstruct.  With a dict `keep`, the sample's
+    scores and its bank's kappa are put there afterwards."""
     import numpy as np
 
     import oracle as O
@@ -156,6 +160,8 @@ def cpu_baseline(workload, n_sample):
     O.reconstruct(U, bank)
     dt = time.perf_counter() - t0
     V = int(np.prod(c["shape"]))
+    if keep is not None:  # the sample's FP64 scores, for the precision table (untimed use)
+        keep.update(pick=pick[:n_sample], U=U, kappa=bank["kappa"], a=bank["a"], params=p, orients=n)
     return {"value": len(sub) * V / dt, "unit": "voxel-orientations/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{len(sub)} of {len(n)} orientations ({len(sub) // 2} antipodal pairs) of the same "
                       f"{'x'.join(map(str, c['shape']))} volume, forward + reconstruct in FP64 numpy "
@@ -344,15 +350,129 @@ def main():
                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                   "frac": a_bytes / (a_ms / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                                   "avg_launch_ms": a_ms, "alg_bytes_per_launch": a_bytes}
+    out["bank_build"]["total_ms"] = bank_total_ms(shape, orients, p)
     if is16 and args.op == "reconstruct":
         out["precision"] = precision_vs_c64(bank, fb, U[0], scales[0], rec[0], args.dtype, ws)
+    extras = (not args.no_extras and args.workload == "C" and args.dtype == "c64" and args.op == "reconstruct")
+    forms = {}
+    if extras:
+        # the c64 scores and reconstruction of the timed steps, then the 16-bit forms
+        keep_gpu = {"c64": (U[0], None, rec[0].clone())}
+        for dt16 in ("bf16", "fp16"):
+            print(f"[bench] form: {dt16} score storage", file=sys.stderr, flush=True)
+            forms[dt16], keep_gpu[dt16] = storage_form(bank, fb, dt16, ws, args, V, No)
     if not args.no_stream_ceiling:
         out["stream_ceiling"] = stream_ceiling(dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample", file=sys.stderr, flush=True)
         n_sample = args.cpu_orients or {"C": 12, "B": 42}[args.workload]
-        out["cpu_baseline"] = cpu_baseline(args.workload, n_sample)
+        sample = {} if extras else None
+        out["cpu_baseline"] = cpu_baseline(args.workload, n_sample, keep=sample)
+        if extras:
+            print("[bench] precision of every storage form against the FP64 oracle", file=sys.stderr, flush=True)
+            out["precision_vs_fp64_oracle"] = precision_vs_oracle(sample, keep_gpu, vol, shape)
+    if extras:
+        del keep_gpu
+        del U
+        torch.cuda.empty_cache()
+        print("[bench] form: differentiation (forward + adjoint of 8 x 128^3)", file=sys.stderr, flush=True)
+        forms["differentiation"] = grad_form(dev, args.warmup, args.steps)
+        for cold in (False, True):
+            print(f"[bench] form: serving, {args.extra_requests} requests, {'cold' if cold else 'warm'} bank cache",
+                  file=sys.stderr, flush=True)
+            forms["serving_cold" if cold else "serving"] = short_serving(dev, args.extra_requests, args.rate, cold)
+        out["forms"] = forms
     print(json.dumps(out), flush=True)
+
+
+def time_steps(step, warmup, steps):
+    """Per-step milliseconds of `steps` calls of step() after `warmup` more,
+    with events on the current stream."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for k in range(steps):
+        step()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    return [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+
+
+def bank_total_ms(shape, orients, p):
+    """The whole bank build (host design, synthesis, band reductions, M and
+    the read-back of kappa), wall clock around os3d.Bank on a second build."""
+    import torch
+    from paper_1505_07690_amd import os3d
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = os3d.Bank(shape, orients, p)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) * 1e3
+    b.close()
+    del b
+    return dt
+
+
+def storage_form(bank, fb, dtype, ws, args, V, No):
+    """The same step with 16-bit score storage: timing and its scores and
+    reconstruction (kept on the device for the precision table)."""
+    import numpy as np
+    import torch
+    from paper_1505_07690_amd import os3d
+    shape = bank.shape
+    Uq = torch.empty((1, No) + shape, dtype=torch.int32, device=fb.device)
+    sc = torch.empty((1, No), dtype=torch.float32, device=fb.device)
+    rq = torch.empty((1,) + shape, dtype=torch.float32, device=fb.device)
+
+    def step():
+        os3d.forward(fb, bank, dtype=dtype, ws=ws, out=Uq, scales=sc)
+        os3d.reconstruct(Uq, bank, scales=sc, dtype=dtype, ws=ws, out=rq)
+
+    per = time_steps(step, args.warmup, args.steps)
+    ms = sum(per) / len(per)
+    alg = V * No * 2 * 4 + 8 * V
+    return ({"ms_per_step": ms, "p50_ms": float(np.percentile(per, 50)), "p99_ms": float(np.percentile(per, 99)),
+             "value": V * No / (ms / 1e3), "unit": "voxel-orientations/s",
+             "step_roofline_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_step": alg},
+            (Uq[0], sc[0], rq[0]))
+
+
+def precision_vs_oracle(sample, keep_gpu, vol, shape, n_freq=100_000):
+    """Relative L2 error of each storage form against the FP64 oracle:
+    scores on the oracle's timed sample of orientations (its bank's kappa
+    rescaled to the full set's, computed by the oracle over the band), and
+    the reconstruction in the frequency domain at uniformly sampled
+    frequencies (by Parseval an estimate of the volume's relative L2 error)
+    against F M / max(M, eps) with M from the oracle."""
+    import numpy as np
+    import oracle as O
+    from paper_1505_07690_amd import os3d
+    t0 = time.perf_counter()
+    n, a, p = sample["orients"], sample["a"], sample["params"]
+    kappa = O.band_kappa_streamed(shape, n, a, p)
+    Uo = sample["U"] * (kappa / sample["kappa"])
+    V = int(np.prod(shape))
+    idx = np.unique(np.random.default_rng(13).integers(0, V, n_freq))
+    M = O.M_at(shape, idx, n, a, p, kappa)
+    F = O.dft3(vol.astype(np.float64)).ravel()[idx]
+    want = F * M / np.maximum(M, p.eps)
+    out = {"vs": "FP64 oracle", "score_orientations": [int(i) for i in sample["pick"]],
+           "reconstruction_freqs_sampled": int(idx.size)}
+    for mode, (Ug, sc, rec) in keep_gpu.items():
+        num = den = 0.0
+        for j, i in enumerate(sample["pick"]):
+            u = Ug[i] if sc is None else os3d.unpack16(Ug[i], sc[i], mode)
+            d = u.cpu().numpy().astype(np.complex128) - Uo[j]
+            num += float(np.sum(np.abs(d) ** 2))
+            den += float(np.sum(np.abs(Uo[j]) ** 2))
+        got = O.dft3(rec.cpu().numpy().astype(np.float64)).ravel()[idx]
+        out[mode] = {"rel_l2_U": (num / den) ** 0.5,
+                     "rel_l2_reconstruction": float(np.linalg.norm(got - want) / np.linalg.norm(want))}
+    out["host_s"] = time.perf_counter() - t0
+    return out
 
 
 def precision_vs_c64(bank, fb, Uq, sc, rec16, dtype, ws):
@@ -447,30 +567,101 @@ def grad_main(args, dev):
     print(json.dumps(out), flush=True)
 
 
-def stream_ceiling(dev, nbytes=2 << 30, reps=10):
-    """HBM rates a plain device copy, read (sum) and write (fill) reach on
-    this GPU with torch's own kernels over 2 GiB buffers: the practical
-    ceiling the kernels' rates compare with (the spec peak is 8 TB/s)."""
+def grad_form(dev, warmup, steps):
+    """The differentiation workload's step (forward + adjoint of a batch of
+    8 volumes of 128^3, N_o = 42, L = 16) for the default bench line."""
+    import numpy as np
     import torch
+    from paper_1505_07690_amd import inputs, os3d
+    c = inputs.CONFIGS["B"]
+    shape, B = c["shape"], 8
+    orients = inputs.icosahedral_orientations(c["level"])
+    No, V = len(orients), int(np.prod(shape))
+    bank = os3d.Bank(shape, orients, os3d.make_params(L=c["L"], s_theta=inputs.s_theta_for(No)))
+    f = torch.from_numpy(np.stack([inputs.tubes(shape, c["tubes"], c["sigma"], c["noise"], c["pairs"], 30 + b)
+                                   for b in range(B)])).to(dev)
+    U = torch.empty((B, No) + shape, dtype=torch.complex64, device=dev)
+    g = torch.empty((B,) + shape, dtype=torch.float32, device=dev)
+    ws = bank.workspace()
+
+    def step():
+        os3d.forward(f, bank, ws=ws, out=U)
+        os3d.adjoint(U, bank, ws=ws, out=g)
+
+    per = time_steps(step, warmup, steps)
+    ms = sum(per) / len(per)
+    alg = B * (V * No * 2 * 8 + 8 * V)
+    out = {"workload": WORKLOADS["D"], "ms_per_step": ms, "p50_ms": float(np.percentile(per, 50)),
+           "p99_ms": float(np.percentile(per, 99)), "value": B * V * No / (ms / 1e3), "unit": "voxel-orientations/s",
+           "step_roofline_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    del U, g, f, bank, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def short_serving(dev, n_requests, rate, cold, budget_gb=160.0, slots=4, max_batch=8):
+    """A short Poisson stream of the serving workload through the
+    continuous-batching server: latency percentiles and throughput, with
+    the banks of every key built beforehand (warm) or during the stream
+    (cold)."""
+    import numpy as np
+    import torch
+    from paper_1505_07690_amd import inputs, serve
+    reqs = inputs.serving_stream(n_requests, rate, seed=4)
+    pool = {sh: [inputs.tubes_device(sh, 12, (1.0, 3.0), 0.2, 0, 1000 + 17 * i + k, device=dev) for k in range(2)]
+            for i, sh in enumerate(inputs.SERVING_SHAPES)}
+    torch.cuda.synchronize()
+    srv = serve.Server(int(budget_gb * (1 << 30)), n_slots=slots, max_batch=max_batch)
+    if not cold:
+        for key in sorted({(sh, n, L) for (_, sh, n, L, _) in reqs}):
+            srv.submit(pool[key[0]][0], key[1], key[2]).result()
+        srv.records.clear()
+        srv.bank_hits = srv.bank_misses = 0
+        srv.bank_build_s.clear()
+    t0 = time.perf_counter()
+    for (t, sh, n, L, seed) in reqs:
+        dt = t0 + t - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        srv.submit(pool[sh][seed % 2], n, L)
+    srv.close()
+    st = srv.stats()
+    out = {k: st.get(k) for k in ("jobs", "ok", "p50_ms", "p99_ms", "mean_wait_ms", "vo_per_s", "mean_batch",
+                                  "bank_hit_rate", "bank_builds", "bank_build_ms_max", "peak_bytes")}
+    out.update(requests=n_requests, rate_per_s=rate, warm_bank_cache=not cold, slots=slots)
+    del srv, pool
+    torch.cuda.empty_cache()
+    return out
+
+
+def stream_ceiling(dev, nbytes=2 << 30, reps=10):
+    """HBM rates the library's own plain copy, read, non-temporal read and
+    write kernels (os3d_stream_probe) reach on this GPU over 2 GiB buffers:
+    the practical ceilings the transform's passes compare with (the spec
+    peak is 8 TB/s)."""
+    import torch
+    from paper_1505_07690_amd import os3d
     a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
+    part = torch.empty(2048, dtype=torch.float32, device=dev)
 
-    def rate(fn, moved):
-        fn()
+    def rate(kind, src, dst, moved):
+        os3d.stream_probe(kind, src, dst)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            fn()
+            os3d.stream_probe(kind, src, dst)
         e1.record()
         torch.cuda.synchronize()
         return moved * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
 
-    out = {"copy_GBs": rate(lambda: b.copy_(a), 2 * nbytes),
-           "read_GBs": rate(lambda: a.sum(), nbytes),
-           "write_GBs": rate(lambda: b.fill_(1.0), nbytes),
-           "buffer_bytes": nbytes}
-    del a, b
+    out = {"copy_GBs": rate("copy", a, b, 2 * nbytes),
+           "read_GBs": rate("read", a, part, nbytes),
+           "read_nt_GBs": rate("read_nt", a, part, nbytes),
+           "write_GBs": rate("write", None, b, nbytes),
+           "buffer_bytes": nbytes, "kernels": "os3d_stream_probe (float4 grid-stride loops, 2048 x 512 threads)"}
+    del a, b, part
     torch.cuda.empty_cache()
     return out
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libos3d.so")
 
 SOURCES = ["os3d_api.cpp", "host_setup.cpp", "kernels_bank.hip", "kernels_fft.hip", "kernels_fft4.hip",
-           "kernels_plane.hip", "noalloc.hip"]
+           "kernels_plane.hip", "noalloc.hip", "kernels_stream.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

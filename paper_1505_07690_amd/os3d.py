@@ -64,6 +64,7 @@ _SIGS = {
                                 ctypes.c_void_p, ctypes.c_void_p],
     "os3d_process": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
+    "os3d_stream_probe": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p],
     "os3d_profile_enable": [ctypes.c_int32],
     "os3d_profile_count": [ctypes.POINTER(ctypes.c_int32)],
     "os3d_profile_get": [ctypes.c_int32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_int64),
@@ -392,6 +393,17 @@ def unpack16(Uq, scales, dtype):
     v = q.view(t).to(torch.float32)
     s = scales.reshape(scales.shape + (1,) * (Uq.dim() - scales.dim())).to(torch.float32)
     return torch.complex(v[..., 0] * s, v[..., 1] * s)
+
+
+STREAM_KINDS = {"copy": 0, "read": 1, "write": 2, "read_nt": 3}
+
+
+def stream_probe(kind, src, dst, stream=None):
+    """One pass of the library's plain copy / read / write kernel over the
+    device tensors (measurement support)."""
+    nbytes = (dst if kind == "write" else src).numel() * (dst if kind == "write" else src).element_size()
+    _check(lib().os3d_stream_probe(STREAM_KINDS[kind], ctypes.c_void_p(src.data_ptr() if src is not None else 0),
+                                   ctypes.c_void_p(dst.data_ptr()), nbytes, _stream_ptr(stream)))
 
 
 def profile_enable(on=True, kernel=None):

@@ -28,7 +28,7 @@ def declared_symbols():
 def test_library_exports_every_declared_symbol():
     L = os3d.lib()
     syms = declared_symbols()
-    assert len(syms) == 20, syms
+    assert len(syms) == 21, syms
     for s in syms:
         assert hasattr(L, s), s
     assert L.os3d_version().decode().startswith("os3d")
