@@ -12,13 +12,20 @@
 // A workgroup is 1024 threads working on four independent sub-problems of
 // 16 x 256 values (four z planes on the natural side, four kx on the
 // frequency side).  Every thread holds 16 values in registers; each pass is
-// three radix-16 DFTs separated by two LDS exchanges.  T is laid out so that
-// both passes move runs of 16 consecutive values (128 bytes):
+// three radix-16 DFTs separated by two LDS exchanges.  A workgroup of the
+// writing pass and one of the reading pass share 16 values of T (128
+// bytes); T groups four such runs of neighbouring reading workgroups, so
+// that the writer stores runs of 512 bytes and the reader loads 128-byte
+// runs that come four to a 512-byte block:
 //   inverse direction (frequency -> space), written by the frequency side:
-//     T[((k2 * 64 + zb) * 16 + n1) * 1024 + kxb * 16 + zz * 4 + kxx]
+//     T[((k2 * 16 + zbh) * 16 + n1) * 4096 + kxb * 64 + zbl * 16 + zz * 4 + kxx]
 //   forward direction (space -> frequency), written by the natural side:
-//     T[((k2 * 64 + kxb) * 16 + n1) * 1024 + z * 4 + kxx]
-// with z = 4 zb + zz and kx = 4 kxb + kxx.
+//     T[((k2 * 16 + kbh) * 16 + n1) * 4096 + zb * 64 + kbl * 16 + zz * 4 + kxx]
+// with z = 4 zb + zz, zb = 4 zbh + zbl, kx = 4 kxb + kxx, kxb = 4 kbh + kbl.
+// (Measured on the writes alone: the frequency side, whose workgroups loop
+// over the pairs of a launch, stores 128-byte runs at 2.9 TB/s and
+// 512-byte runs at 5.4 TB/s; the reads keep the rate of whole 128 KB tiles
+// when the four readers of a block run side by side, see reader_tile.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,13 +55,32 @@ __device__ __forceinline__ float block_sum_1024(float v, float* red) {
   return s;
 }
 
+// Tile of a natural-side workgroup of the inverse direction.  The four tiles
+// zb = 4 zbh + zbl (zbl = 0..3) read the four 128-byte quarters of the same
+// 512-byte blocks of T; workgroups are dispatched to the eight XCDs in turn
+// (blockIdx mod 8), so the four go to consecutive slots of one XCD and run
+// side by side (measured: 3.09 against 3.58 ms per launch of 40 pairs when
+// they land on four different XCDs).
+__device__ __forceinline__ int reader_tile(int b) {
+  const int xcd = b & 7, i = b >> 3;
+  return (((i >> 2) << 3) + xcd) * 4 + (i & 3);
+}
+
+// exp(sg 2 pi i m / 256) for the direction sg of the kernel (the table holds sg = -1)
+template <int SG>
 __device__ __forceinline__ void load_twiddles(const PassArgs& a, float2* twl) {
   for (int i = threadIdx.x; i < 256; i += k4Threads) {
     float2 v = a.tw[i];
-    if (a.sgn > 0.f) v.y = -v.y;
+    if (SG > 0) v.y = -v.y;
     twl[i] = v;
   }
 }
+
+// Each kernel runs one direction: the frequency-to-space kernels the inverse
+// DFT (+1), the space-to-frequency kernels the forward DFT (-1).  The sign is
+// a compile-time constant so that the multiplications by +-i and +-1 of the
+// radix-16 butterflies fold into operand negations.
+constexpr float kInv = 1.f, kFwd = -1.f;
 
 // Frequency side of the inverse direction: Phi tile (kxb, n1) -> T.
 // The spectrum tile (F, or X / max(M, eps)) is loaded once for the pair
@@ -70,7 +96,7 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
   const int t = threadIdx.x;
   const int kxb = blockIdx.x & 63, n1 = blockIdx.x >> 6, tile = kxb * 16 + n1;
   const int g = t & 3, s = (t >> 2) & 15, n2 = t >> 6;
-  load_twiddles(a, twl);
+  load_twiddles<1>(a, twl);
   const long long base = (long long)tile << 14;
   float2 spec[16];
   if constexpr (LM == LM_MULBANK) {  // F times the bank's normaliser, once for the launch
@@ -108,7 +134,7 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = spec[r];
     }
-    dft16(v, a.sgn);
+    dft16(v, kInv);
     float2* S = lds + g * k4Sub + n2 * k4LS;
     if (j > 0) __syncthreads();  // the previous pair's step-A reads are done
 #pragma unroll
@@ -118,20 +144,20 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
     for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
 #pragma unroll
     for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
-    dft16(v, a.sgn);
+    dft16(v, kInv);
 #pragma unroll
     for (int r = 0; r < 16; ++r) S[pad4(s + 16 * r)] = v[r];
     __syncthreads();
     float2 u[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) u[q] = lds[g * k4Sub + q * k4LS + pad4(z)];
-    dft16(u, a.sgn);
+    dft16(u, kInv);
 #pragma unroll
     for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[n1 * k2]);
     float2* T = a.dst_c + (long long)j * a.dst_stride;
-    const long long o = (long long)n1 * 1024 + kxb * 16 + zz * 4 + g;
+    const long long o = (long long)((zb >> 2) * 16 + n1) * 4096 + kxb * 64 + (zb & 3) * 16 + zz * 4 + g;
 #pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) T[((long long)(k2 * 64 + zb) * 16) * 1024 + o] = u[k2];
+    for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = u[k2];
   }
 }
 
@@ -142,14 +168,15 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
   const int t = threadIdx.x;
-  const int tile = blockIdx.x, k2 = tile >> 6, zb = tile & 63;
+  const int tile = reader_tile(blockIdx.x), k2 = tile >> 6, zb = tile & 63;
   const int j = blockIdx.y;
-  load_twiddles(a, twl);
-  const float2* T = a.src_c + (long long)j * a.src_stride + (long long)tile * 16 * 1024;
+  load_twiddles<1>(a, twl);
+  const float2* T = a.src_c + (long long)j * a.src_stride + (long long)(k2 * 16 + (zb >> 2)) * 16 * 4096 +
+                    (t >> 4) * 64 + (zb & 3) * 16 + (t & 15);
   float2 v[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) v[q] = T[q * 1024 + t];
-  dft16(v, a.sgn);  // over n1 -> k1
+  for (int q = 0; q < 16; ++q) v[q] = T[q * 4096];
+  dft16(v, kInv);  // over n1 -> k1
   {
     const int g = (t >> 2) & 3, kx = (t >> 4) * 4 + (t & 3);
 #pragma unroll
@@ -160,7 +187,7 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
   float2* S = lds + g * k4Sub + k1 * k4LS;
 #pragma unroll
   for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
-  dft16(v, a.sgn);
+  dft16(v, kInv);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
@@ -169,7 +196,7 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
   for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
 #pragma unroll
   for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
-  dft16(v, a.sgn);
+  dft16(v, kInv);
   const long long row = ((long long)(4 * zb + g) * 256 + (16 * k1 + k2)) * 256;
   float2 dummy[16];
   store_k<SM, DT, 16>(a, j, row + s, 16, v, dummy);
@@ -186,13 +213,13 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
   const int t = threadIdx.x;
   const int zb = blockIdx.x >> 4, n1 = blockIdx.x & 15;
   const int j = blockIdx.y;
-  load_twiddles(a, twl);
+  load_twiddles<-1>(a, twl);
   const int g = t >> 8, n2 = (t >> 4) & 15, s = t & 15;
   const long long row = ((long long)(4 * zb + g) * 256 + (n1 + 16 * n2)) * 256;
   float2 v[16];
   float asum = 0.f;
   load_k<LM, DT, 16>(a, j, row + s, 16, v, asum);
-  dft16(v, a.sgn);
+  dft16(v, kFwd);
   float2* S = lds + g * k4Sub + n2 * k4LS;
 #pragma unroll
   for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
@@ -201,7 +228,7 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
   for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
 #pragma unroll
   for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
-  dft16(v, a.sgn);
+  dft16(v, kFwd);
 #pragma unroll
   for (int r = 0; r < 16; ++r) S[pad4(s + 16 * r)] = v[r];
   __syncthreads();
@@ -209,13 +236,13 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
   float2 u[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) u[q] = lds[zz * k4Sub + q * k4LS + pad4(kx)];
-  dft16(u, a.sgn);
+  dft16(u, kFwd);
 #pragma unroll
   for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[n1 * k2]);
   float2* T = a.dst_c + (long long)j * a.dst_stride;
-  const long long o = (long long)n1 * 1024 + (4 * zb + zz) * 4 + kxx;
+  const long long o = (long long)((kxb >> 2) * 16 + n1) * 4096 + zb * 64 + (kxb & 3) * 16 + zz * 4 + kxx;
 #pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) T[((long long)(k2 * 64 + kxb) * 16) * 1024 + o] = u[k2];
+  for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = u[k2];
 }
 
 // Natural side of both directions, for processing via scores: inverse T
@@ -228,13 +255,14 @@ __global__ __launch_bounds__(k4Threads) void k4_nat_phi(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];  // exp(-2 pi i m / 256); conjugated for the inverse direction
   const int t = threadIdx.x;
-  const int tile = blockIdx.x, c = tile >> 6, zb = tile & 63;
+  const int tile = reader_tile(blockIdx.x), c = tile >> 6, zb = tile & 63;
   const int j = blockIdx.y;
   for (int i = t; i < 256; i += k4Threads) twl[i] = a.tw[i];
-  const float2* T = a.src_c + (long long)j * a.src_stride + (long long)tile * 16 * 1024;
+  const float2* T = a.src_c + (long long)j * a.src_stride + (long long)(c * 16 + (zb >> 2)) * 16 * 4096 +
+                    (t >> 4) * 64 + (zb & 3) * 16 + (t & 15);
   float2 v[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) v[q] = T[q * 1024 + t];
+  for (int q = 0; q < 16; ++q) v[q] = T[q * 4096];
   dft16(v, 1.f);  // over n1 -> k1
   {
     const int g = (t >> 2) & 3, kx = (t >> 4) * 4 + (t & 3);
@@ -281,9 +309,9 @@ __global__ __launch_bounds__(k4Threads) void k4_nat_phi(PassArgs a) {
 #pragma unroll
   for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[c * k2]);
   float2* Tf = a.dst_c + (long long)j * a.dst_stride;
-  const long long o = (long long)c * 1024 + (4 * zb + zz) * 4 + kxx;
+  const long long o = (long long)((kxb >> 2) * 16 + c) * 4096 + zb * 64 + (kxb & 3) * 16 + zz * 4 + kxx;
 #pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) Tf[((long long)(k2 * 64 + kxb) * 16) * 1024 + o] = u[k2];
+  for (int k2 = 0; k2 < 16; ++k2) Tf[(long long)k2 * (256 * 4096) + o] = u[k2];
 }
 
 // Frequency side of the forward direction: T tile (k2, kxb) -> Phi tile
@@ -295,7 +323,7 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
   __shared__ float2 twl[256];
   const int t = threadIdx.x;
   const int tile = blockIdx.x, k2 = tile >> 6, kxb = tile & 63;
-  load_twiddles(a, twl);
+  load_twiddles<-1>(a, twl);
   const long long pbase = (long long)(kxb * 16 + k2) << 14;
   const int jb = (SM == SM_ACCUM) ? 0 : blockIdx.y;
   const int je = (SM == SM_ACCUM) ? a.nb : blockIdx.y + 1;
@@ -303,11 +331,12 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = make_float2(0.f, 0.f);
   for (int j = jb; j < je; ++j) {
-    const float2* T = a.src_c + (long long)j * a.src_stride + (long long)tile * 16 * 1024;
+    const float2* T = a.src_c + (long long)j * a.src_stride + (long long)(k2 * 16 + (kxb >> 2)) * 16 * 4096 +
+                      (t >> 4) * 64 + (kxb & 3) * 16 + (t & 15);
     float2 v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = ldnt(T + q * 1024 + t);
-    dft16(v, a.sgn);  // over n1 -> k1
+    for (int q = 0; q < 16; ++q) v[q] = ldnt(T + q * 4096);
+    dft16(v, kFwd);  // over n1 -> k1
     {
       const int g = t & 3, z = t >> 2;
 #pragma unroll
@@ -318,7 +347,7 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
     float2* S = lds + g * k4Sub + k1 * k4LS;
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
-    dft16(v, a.sgn);
+    dft16(v, kFwd);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
@@ -327,7 +356,7 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
     for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
 #pragma unroll
     for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twl[s * r]);
-    dft16(v, a.sgn);
+    dft16(v, kFwd);
     // kz = s + 16 r sits at Phi position pbase + r * 1024 + t
     store_k<SM, OS3D_C64, 16>(a, j, pbase + t, 1024, v, acc);
     if constexpr (SM == SM_ACCUM) __syncthreads();
