@@ -660,7 +660,7 @@ def stream_ceiling(dev, nbytes=2 << 30, reps=10):
            "read_GBs": rate("read", a, part, nbytes),
            "read_nt_GBs": rate("read_nt", a, part, nbytes),
            "write_GBs": rate("write", None, b, nbytes),
-           "buffer_bytes": nbytes, "kernels": "os3d_stream_probe (float4 grid-stride loops, 2048 x 512 threads)"}
+           "buffer_bytes": nbytes, "kernels": "os3d_stream_probe (one-shot grids, four float4 per thread; the copy with non-temporal loads)"}
     del a, b, part
     torch.cuda.empty_cache()
     return out

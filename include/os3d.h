@@ -242,9 +242,9 @@ os3d_status os3d_profile_get(int32_t idx, const char** name, int64_t* launches, 
 /* Streaming probe (measurement support, not a method step): one pass of a
  * plain kernel over `bytes` bytes on `stream`, to measure the HBM rates a
  * copy, a read and a write reach on this GPU.  kind 0: copy src -> dst;
- * 1: read src (dst receives 2048 per-workgroup float sums, so it must hold
- * 8 KiB); 2: write dst (src unused, may be NULL); 3: read src with
- * non-temporal loads (dst as for 1).  bytes must be a positive multiple of
+ * 1: read src (dst receives up to 2048 float values that keep the loads
+ * live, so it must hold 8 KiB); 2: write dst (src unused, may be NULL);
+ * 3: read src with non-temporal loads (dst as for 1).  bytes must be a positive multiple of
  * 16 and the buffers 16-byte aligned device memory, else OS3D_EINVAL. */
 os3d_status os3d_stream_probe(int32_t kind, const void* src, void* dst, size_t bytes, void* stream);
 
