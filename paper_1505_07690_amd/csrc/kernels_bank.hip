@@ -215,25 +215,39 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
         }
         const float* Sc = Scos;
         const float* Ss = Scos + half;  // the sin rows follow the cos rows
+        // the cos rows, then (m > 0: m is uniform, a scalar branch) the sin
+        // rows, which are zero for m = 0; two loops also keep fewer steering
+        // values live than one loop over both (measured 25.9 against 26.6 ms
+        // at 256^3 x 81 rows, L = 24)
         for (int k0 = 0; k0 < qpad; k0 += 4) {
           const int kr = k0 + (lane >> 4);
-          float q[4], bc[CB], bs[CB];
+          float q[4], bc[CB];
 #pragma unroll
           for (int r = 0; r < 4; ++r) q[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
 #pragma unroll
-          for (int c = 0; c < CB; ++c) {
-            bc[c] = Sc[kr * kCols + c * 16 + (lane & 15)];
-            bs[c] = Ss[kr * kCols + c * 16 + (lane & 15)];
-          }
-          // all column blocks, also past Npad (zero columns); for m = 0 the
-          // sin rows are zero: no branch between the MFMAs
+          for (int c = 0; c < CB; ++c) bc[c] = Sc[kr * kCols + c * 16 + (lane & 15)];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const float ac = q[r] * crv[r], as = q[r] * civ[r];
+            const float ac = q[r] * crv[r];
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
+            for (int c = 0; c < CB; ++c)
               acc[w][r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac, bc[c], acc[w][r][c], 0, 0, 0);
-              acc[w][r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bs[c], acc[w][r][c], 0, 0, 0);
+          }
+        }
+        if (m > 0) {
+          for (int k0 = 0; k0 < qpad; k0 += 4) {
+            const int kr = k0 + (lane >> 4);
+            float q[4], bs[CB];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) q[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) bs[c] = Ss[kr * kCols + c * 16 + (lane & 15)];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const float as = q[r] * civ[r];
+#pragma unroll
+              for (int c = 0; c < CB; ++c)
+                acc[w][r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bs[c], acc[w][r][c], 0, 0, 0);
             }
           }
         }
