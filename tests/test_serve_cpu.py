@@ -323,3 +323,25 @@ def test_a_slow_bank_build_does_not_stall_other_keys():
         st = s.stats()
     assert t_fast < 0.3, t_fast
     assert st["ok"] == 7 and st["bank_builds"] == 2 and st["bank_build_ms_max"] >= 500
+
+
+def test_results_are_handed_to_the_submitting_stream():
+    """An executor that knows streams gets each result handed over to the
+    stream its job was submitted from, before the Future resolves."""
+    class StreamExecutor(FakeExecutor):
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.handed = []
+
+        def consumer_stream(self, volume):
+            return ("stream of", threading.get_ident())
+
+        def hand_over(self, result, stream):
+            self.handed.append((id(result), stream))
+
+    ex = StreamExecutor(2, run_s=0.005)
+    with Server(1 << 30, n_slots=2, executor=ex) as s:
+        futs = [s.submit(vol((8, 8, 8), i), 42, 16) for i in range(3)]
+        outs = [f.result(timeout=5) for f in futs]
+    assert sorted(h[0] for h in ex.handed) == sorted(id(o) for o in outs)
+    assert all(h[1] == ("stream of", threading.get_ident()) for h in ex.handed)
