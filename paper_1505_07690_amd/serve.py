@@ -330,7 +330,8 @@ class Server:
                 break
             e = self._banks.pop(k)
             self._account(-e.nbytes)
-            self.ex.free_bank(e.bank)
+            if e.bank is not None:  # None: a failed build, nothing to free
+                self.ex.free_bank(e.bank)
             self.bank_evictions += 1
         return True
 

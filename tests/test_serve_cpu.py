@@ -345,3 +345,22 @@ def test_results_are_handed_to_the_submitting_stream():
         outs = [f.result(timeout=5) for f in futs]
     assert sorted(h[0] for h in ex.handed) == sorted(id(o) for o in outs)
     assert all(h[1] == ("stream of", threading.get_ident()) for h in ex.handed)
+
+
+def test_a_failed_build_left_in_the_cache_is_evictable():
+    """A bank build that fails after its only job has timed out leaves an
+    entry without a bank in the cache; when a later job needs the room, the
+    entry is dropped and nothing is freed for it."""
+    bad = ((16, 16, 16), 42, 16)
+    ex = FakeExecutor(1, run_s=0.005, fail_keys={bad}, build_s={bad: 0.3})
+    big = (32, 32, 32)
+    budget = fp(big, 42) + 1024  # room for one bank and one job of the big shape only
+    with Server(budget, n_slots=1, executor=ex) as s:
+        f_bad = s.submit(vol((16, 16, 16), 1), 42, 16, timeout=0.05)
+        with pytest.raises(JobTimeout):
+            f_bad.result(timeout=5)
+        time.sleep(0.4)  # the build has failed by now, with no job of its key left
+        assert np.array_equal(s.submit(vol(big, 2), 42, 16).result(timeout=5), 2 * vol(big, 2))
+        st = s.stats()
+    assert st["bank_evictions"] >= 1
+    assert None not in ex.freed and bad not in ex.freed
