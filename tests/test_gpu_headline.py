@@ -188,3 +188,27 @@ def test_headline_reconstruction(hl):
         hl["report"].setdefault("rec_rel_l2_near_nyquist", {})[mode] = e_near
     hl["report"]["rec_rel_l2"] = errs
     print("PRECISION " + json.dumps(hl["report"], default=float), flush=True)
+
+
+def test_headline_adjoint_of_one_pair_against_oracle(hl):
+    """W* of a general complex score supported on one antipodal pair (Eq. 8
+    without the division by M), over the whole grid, against the oracle
+    with its own kappa."""
+    torch, os3d, gb, shape = hl["torch"], hl["os3d"], hl["gb"], hl["shape"]
+    n, a, p, kappa = hl["n"], hl["a"], hl["p"], hl["kappa"]
+    i = hl["reps"][40]
+    j = int(hl["partner"][i])
+    rng = np.random.default_rng(9)
+    Ui = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    Uj = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    hl.pop("Us", None)  # free the scores of the other tests
+    Ug = torch.zeros((len(n),) + shape, dtype=torch.complex64, device="cuda")
+    Ug[i] = torch.from_numpy(Ui).cuda()
+    Ug[j] = torch.from_numpy(Uj).cuda()
+    adj = os3d.adjoint(Ug, gb).cpu().numpy()
+    del Ug
+    psi = O.bank_row(shape, n[i], a, p, kappa)
+    X = psi * O.dft3(Ui.astype(np.complex128))
+    psi = np.roll(np.flip(psi, axis=(0, 1, 2)), 1, axis=(0, 1, 2))  # the partner's row: the same row at -k
+    X += psi * O.dft3(Uj.astype(np.complex128))
+    assert rel(adj, np.real(O.idft3(X))) < TOL
