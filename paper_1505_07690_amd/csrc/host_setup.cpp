@@ -275,26 +275,30 @@ void real_sh(const ShTables& t, const double n[3], double* Y) {
   }
 }
 
-KLayout k_layout(int L) {
-  KLayout k;
-  k.L = L;
-  k.off.assign(L + 1, 0);
-  k.len.assign(L + 1, 0);
-  k.pad.assign(L + 1, 0);
-  int o = 0;
-  for (int m = 0; m <= L; ++m) {
-    k.len[m] = (m == 0) ? (L + 1) : 2 * (L + 1 - m);
-    k.pad[m] = (k.len[m] + 3) / 4 * 4;
-    k.off[m] = o;
-    o += k.pad[m];
-  }
-  k.K = o;
-  return k;
-}
+int synth_words(int L) { return (L + 2) / 2 + L * (L + 1) / 2; }
 
-int k_index(const KLayout& kl, int l, int m, bool sin_part) {
-  if (m == 0) return kl.off[0] + l;
-  return kl.off[m] + (sin_part ? (kl.L + 1 - m) : 0) + (l - m);
+int synth_kblocks(int L) { return (synth_words(L) + 15) / 16; }
+
+bool synth_entry(int L, int e, int& l, int& m, bool& sin_part) {
+  const int w = e >> 1, h = e & 1;
+  const int w0 = (L + 2) / 2;
+  sin_part = false;
+  if (w < w0) {  // m = 0: two consecutive l per word
+    m = 0;
+    l = 2 * w + h;
+    return l <= L;
+  }
+  int r = w - w0;
+  for (m = 1; m <= L; ++m) {  // one l per word: (cos, sin)
+    const int n = L + 1 - m;
+    if (r < n) {
+      l = m + r;
+      sin_part = (h == 1);
+      return true;
+    }
+    r -= n;
+  }
+  return false;
 }
 
 void steering_std(const os3d_wavelet_params& p, const double* orients, int n, const std::vector<double>& a,

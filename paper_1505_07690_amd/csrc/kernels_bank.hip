@@ -4,21 +4,32 @@
 // rows are one row of a dense contraction
 //     h[k, i] = sum_{(l,m)} Y_lm(w_hat_k) S[(l,m), i]
 // (S: steering matrix a_l sqrt(4 pi/(2l+1)) Y_lm(n_i), the addition-theorem
-// form of the Wigner-D rotation of Eqs. 17-19).  Each workgroup owns 256
-// frequency points: every thread generates its point's associated Legendre
-// values Q_l^m for one order m at a time with the FP64 normalised recursion
-// and rounds them to FP32 into LDS; the real harmonics of that order are
-// Q_l^m times the real and imaginary parts of (x + iy)^m, applied in
-// registers to the MFMA A operand.  The four waves run
-// v_mfma_f32_16x16x4_f32 over the chunk against the chunk's rows of S
-// (prefetched during the recursion and staged in LDS).  The epilogue
-// multiplies by the FP64 radial window g(rho) (Eq. 10), applies the Nyquist
-// and DC rules, writes the bank rows and accumulates sum_i psi_i^2 (Eq. 9)
-// and sum_i psi_i in FP64 with a fixed-order cross-lane tree; the
-// workgroup's sums of both over the normalisation band go to one partial
-// record per workgroup.  The rows are stored without the normaliser kappa
-// (known only once every partial is in): the transforms apply kappa as a
-// scalar where they multiply by the bank.
+// form of the Wigner-D rotation of Eqs. 17-19).  It runs on the fp16 matrix
+// cores with FP32-level accuracy: each operand is split into fp16 hi + lo
+// parts, x = hi + lo to 2^-22 relative, and
+//     x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y
+// (three v_mfma_f32_16x16x32_f16, FP32 accumulation; the dropped lo lo term
+// is below 2^-22 relative).  Y_lm is scaled by 2^13 and S by 2^e_S first so
+// that neither part meets fp16's subnormal range; the product is scaled back
+// by 2^-(13 + e_S).
+//
+// Each wave owns 64 frequency points and works alone: every lane runs the
+// FP64 normalised recursion for its point's Q_l^m, one K entry pair per
+// step, multiplies by Re / Im (x + iy)^m (the sinus power is in that
+// factor), splits into hi / lo and writes the pair to the wave's LDS ring
+// (two K-blocks of 32 entries, [word][point]).  When a K-block is complete
+// the wave reads it back in the MFMA's A-operand order (lane t: point t % 16
+// of each 16-point row block, entries 8 (t / 16) .. + 7) and runs the block
+// against the steering operands, which the host packed in the B-operand
+// order and which the wave loads from memory (L2-resident) while it
+// generates the block.  The epilogue multiplies by the FP64 radial window
+// g(rho) (Eq. 10), applies the Nyquist and DC rules, writes the bank rows
+// and accumulates sum_i psi_i^2 (Eq. 9) and sum_i psi_i in FP64 with a
+// fixed-order cross-lane tree; the workgroup's sums of both over the
+// normalisation band go to one partial record per workgroup.  The rows are
+// stored without the normaliser kappa (known only once every partial is
+// in): the transforms apply kappa as a scalar where they multiply by the
+// bank.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -32,27 +43,29 @@
 namespace os3d {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kBankPts = 256;   // frequency points per workgroup
-constexpr int kYStride = 272;   // LDS row stride (floats) of the K-chunk buffer
-constexpr int kColBlocks = 3;                  // 16-column MFMA blocks per sweep (at most)
-constexpr int kColsPerSweep = 16 * kColBlocks;
-constexpr int kStageRegs = 11;                 // steering values prefetched per thread and chunk
+constexpr int kBankPts = 256;    // frequency points per workgroup (four independent waves)
+constexpr int kRingRows = 32;    // two K-blocks of 16 words
+constexpr int kRingStride = 68;  // words per ring row: rows 4 apart fall 16 banks apart (A reads conflict-free)
+constexpr int kMaxNcb = 6;       // 16-column blocks per sweep
+constexpr double kYScale = 8192.0;  // 2^13
 
 struct BankArgs {
   int layout;  // storage order of the frequency points (natural or four-step tiles)
   int Nz, Ny, Nx;
   long long V;
-  int L, Npad, n_rows, maxpad;
-  double t_inv;      // 1 / t of Eq. (10)
+  int L, n_rows, ncb, kblocks;
+  double t_inv;       // 1 / t of Eq. (10)
   int taylor_N;
-  double dc_value;   // a_0 / sqrt(4 pi)
-  const float* S;    // [K][Npad]
-  const double* tab; // qmm[L+1] | alm[(L+1)^2] | blm[(L+1)^2]
-  const int* koff;   // chunk offsets [L+1] | padded lengths [L+1]
-  float* psi;        // [n_rows][V]
-  double* Mh;        // [V]
-  double* part;      // [gridDim.x][3]: band sums of Mh and of sum_i psi_i, band count
+  double dc_value;    // a_0 / sqrt(4 pi)
+  float out_scale;    // 2^-(13 + e_S)
+  const uint4* S;     // [kblocks][ncb][2 (hi, lo)][64 lanes] B operands
+  const double* tab;  // recursion steps [steps][alpha, beta, gamma, order-start flag]
+  float* psi;         // [n_rows][V]
+  double* Mh;         // [V]
+  double* part;       // [gridDim.x][3]: band sums of Mh and of sum_i psi_i, band count
 };
 
 __device__ inline double omega_of(int k, int n) {
@@ -73,33 +86,53 @@ __device__ inline double radial_g(double rho2, double t_inv, int N) {
   return acc;
 }
 
-// One K-chunk per m: the rows Q_l^m (l = m..L, times sqrt 2 for m > 0) of
-// the 256 points are generated once into LDS; the cos rows of the chunk are
-// Q cos(m phi) and the sin rows Q sin(m phi), so the A operand of either half
-// is the same LDS value times the point's (x + iy)^m real or imaginary part,
-// applied in registers.  Half the LDS of storing both halves: three
-// workgroups per CU.
-template <int NS, int CB>
-__global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
-  extern __shared__ float Ybuf[];  // [qpad_max][kYStride], then cos and sin steering rows [2][qpad_max][cols]
+// fp16 hi / lo parts of two values (round to nearest even both times),
+// packed low half first.
+__device__ __forceinline__ void split_pair(float u, float v, unsigned& hi, unsigned& lo) {
+  const _Float16 hu = (_Float16)u, hv = (_Float16)v;
+  const _Float16 lu = (_Float16)(u - (float)hu), lv = (_Float16)(v - (float)hv);
+  hi = (unsigned)__builtin_bit_cast(unsigned short, hu) | ((unsigned)__builtin_bit_cast(unsigned short, hv) << 16);
+  lo = (unsigned)__builtin_bit_cast(unsigned short, lu) | ((unsigned)__builtin_bit_cast(unsigned short, lv) << 16);
+}
+
+// The recursion steps in the synthesis order, one record of four doubles
+// per step: Q = alpha (z Q' - beta Q'') + gamma (Q', Q'': the two previous
+// values of the order), and a nonzero fourth word where an order m >= 1
+// starts.  m = 0 takes two steps per word (the last one zero when L is
+// even), every later order one step per word.  The table is read-only
+// during the synthesis: read through the constant address space, its
+// uniform records become scalar loads, which do not wait behind the vector
+// loads of the steering operands.
+typedef const double __attribute__((address_space(4)))* ctab_t;
+typedef const long long __attribute__((address_space(4)))* cflag_t;
+
+__device__ __forceinline__ double rec_step(ctab_t r, double uz, double& q1, double& q2) {
+  const double q = fma(r[0], fma(uz, q1, -r[1] * q2), r[2]);
+  q2 = q1;
+  q1 = q;
+  return q;
+}
+
+template <int NCB>
+__global__ __launch_bounds__(256, 2) void k_bank_synth(BankArgs a) {
+  __shared__ unsigned ring[4][2][kRingRows * kRingStride];  // per wave: hi plane, lo plane
   __shared__ double gsh[kBankPts];
   __shared__ double Msh[kBankPts];
-  __shared__ double Ash[kBankPts];
-  __shared__ float crsh[kBankPts], cish[kBankPts];
-  __shared__ int dcsh[kBankPts], bandsh[kBankPts];
+  __shared__ int flags[kBankPts];  // bit 0: DC, bit 1: in the normalisation band
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long long p0 = (long long)blockIdx.x * kBankPts;
+  const long long pw = p0 + wave * 64;  // the wave's first point
   const long long p = p0 + tid;
   const bool valid = p < a.V;
-  const int L = a.L, nn = L + 1;
-  const double* qmm = a.tab;
-  const double* alm = a.tab + nn;
-  const double* blm = a.tab + nn + nn * nn;
-  const int* koff = a.koff;
-  float* Scos = Ybuf + a.maxpad * kYStride;
+  const int L = a.L;
+  const ctab_t tab = (ctab_t)a.tab;
+  const int w0 = (L + 2) / 2;              // words of order m = 0
+  const int nwords = w0 + L * (L + 1) / 2;
+  unsigned* hiP = ring[wave][0];
+  unsigned* loP = ring[wave][1];
 
-  // this thread's frequency point
+  // this lane's frequency point
   double ux = 0.0, uy = 0.0, uz = 1.0, g = 0.0;
   int dc = 0;
   bool band = false;  // the normalisation band: 0 < rho <= rho_N / 2, no Nyquist plane
@@ -122,211 +155,187 @@ __global__ __launch_bounds__(256, 3) void k_bank_synth(BankArgs a) {
     band = !nyq && r2 > 0.0 && r2 <= hn * hn;
   }
   gsh[tid] = g;
-  dcsh[tid] = dc;
-  bandsh[tid] = band ? 1 : 0;
+  flags[tid] = dc | (band ? 2 : 0);
   Msh[tid] = 0.0;
   double asum = 0.0;  // this lane's share of the band sum of sum_i psi_raw
+  // the points are wave-private: a wave-level fence orders the LDS traffic
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-  constexpr int kCols = 16 * CB;  // columns per sweep
-  // NS sweeps of kCols columns share each order's recursion: one FP64 pass of
-  // Q_l^m per order and column group, the steering rows of every sweep
-  // staged in turn
-  // steering values prefetched in registers during the recursion (fewer when
-  // two sweeps' accumulators are live)
-  constexpr int SR = (NS == 1) ? kStageRegs : 4;
-  for (int c0 = 0; c0 < a.Npad; c0 += NS * kCols) {
-    floatx4 acc[NS][4][CB];
+  const bool vec_store = (a.V % 4 == 0) && (pw + 64 <= a.V);
+  for (int cb0 = 0; cb0 < a.ncb; cb0 += NCB) {
+    const int nact = min(NCB, a.ncb - cb0);  // uniform
+    floatx4 acc[4][NCB];
 #pragma unroll
-    for (int w = 0; w < NS; ++w)
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    double q1 = 0.0, q2 = 0.0;        // the recursion's two previous values
+    double cr = 1.0, ci = 0.0;        // (x + iy)^m
+    float crs = 0.f, cis = 0.f;       // (x + iy)^m times sqrt 2 and 2^13, in FP32
+    for (int kb = 0; kb < a.kblocks; ++kb) {
+      // the block's steering operands: in flight while the block is generated
+      uint4 bop[NCB][2];
+#pragma unroll
+      for (int c = 0; c < NCB; ++c)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          bop[c][h] = (c < nact) ? a.S[(((long long)kb * a.ncb + cb0 + c) * 2 + h) * 64 + lane]
+                                 : uint4{0u, 0u, 0u, 0u};
+      // generate the block's 16 words (uniform control flow)
+      const int rb = (kb & 1) * 16;
+#pragma unroll 2
+      for (int w = 0; w < 16; ++w) {
+        const int gw = kb * 16 + w;
+        float u = 0.f, v = 0.f;
+        if (gw < w0) {  // m = 0: two consecutive l per word
+          const ctab_t r = tab + 8 * gw;
+          u = (float)(rec_step(r, uz, q1, q2) * kYScale);
+          v = (float)(rec_step(r + 4, uz, q1, q2) * kYScale);
+        } else if (gw < nwords) {  // one l per word: cos and sin parts
+          const int st = w0 + gw;  // 2 w0 steps of m = 0 before
+          if (((cflag_t)tab)[4 * st + 3] != 0) {  // order m starts: (x + iy)^m
+            const double nr = cr * ux - ci * uy, ni = cr * uy + ci * ux;
+            cr = nr;
+            ci = ni;
+            const double sc = 1.4142135623730950488 * kYScale;
+            crs = (float)(nr * sc);
+            cis = (float)(ni * sc);
+          }
+          const float q = (float)rec_step(tab + 4 * st, uz, q1, q2);
+          u = q * crs;
+          v = q * cis;
+        }
+        unsigned hw, lw;
+        split_pair(u, v, hw, lw);
+        hiP[(rb + w) * kRingStride + lane] = hw;
+        loP[(rb + w) * kRingStride + lane] = lw;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // A operands of the four 16-point row blocks
+      half8 ah[4], al[4];
+      const int r0 = rb + 4 * (lane >> 4);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = r * 16 + (lane & 15);
+        uint4 h4, l4;
+        h4.x = hiP[(r0 + 0) * kRingStride + col];
+        h4.y = hiP[(r0 + 1) * kRingStride + col];
+        h4.z = hiP[(r0 + 2) * kRingStride + col];
+        h4.w = hiP[(r0 + 3) * kRingStride + col];
+        l4.x = loP[(r0 + 0) * kRingStride + col];
+        l4.y = loP[(r0 + 1) * kRingStride + col];
+        l4.z = loP[(r0 + 2) * kRingStride + col];
+        l4.w = loP[(r0 + 3) * kRingStride + col];
+        ah[r] = __builtin_bit_cast(half8, h4);
+        al[r] = __builtin_bit_cast(half8, l4);
+      }
+      // hi hi, hi lo, lo hi: each pass over all 4 x NCB accumulators before
+      // the next touches one again (the operands of absent column blocks are
+      // zero: no branches between the MFMAs)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < CB; ++c) acc[w][r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    double cr = 1.0, ci = 0.0;  // (x + i y)^m of the unit frequency direction
-    for (int m = 0; m <= L; ++m) {
-      if (m > 0) {
-        double nr = cr * ux - ci * uy, ni = cr * uy + ci * ux;
-        cr = nr;
-        ci = ni;
-      }
-      const int nq = nn - m;            // rows l = m..L
-      const int qpad = (nq + 3) & ~3;
-      // issue the loads of the chunk's cos and sin steering rows (the first
-      // sweep's columns) first, branch-free, so that they complete during
-      // the recursion
-      const float* Sm = a.S + (long long)koff[m] * a.Npad;
-      const int half = qpad * kCols;
-      float sv[SR];
+        for (int c = 0; c < NCB; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], __builtin_bit_cast(half8, bop[c][0]), acc[r][c], 0, 0,
+                                                             0);
 #pragma unroll
-      for (int u = 0; u < SR; ++u) {
-        const int idx = u * kBankPts + tid;
-        const int part = idx >= half, id2 = idx - part * half;
-        const int kr = id2 / kCols, cc = id2 - kr * kCols;
-        const bool ok = idx < 2 * half && kr < nq && c0 + cc < a.Npad && (m > 0 || part == 0);
-        const float v = Sm[ok ? (long long)(kr + part * nq) * a.Npad + c0 + cc : 0];
-        sv[u] = ok ? v : 0.f;
-      }
-      // Q_l^m for l = m..L (sinus power factored out), FP64 recursion
-      {
-        double q2 = 0.0, q1 = qmm[m];
-        const double sc = (m == 0) ? 1.0 : 1.4142135623730950488;
-        for (int l = m; l <= L; ++l) {
-          double q;
-          if (l == m)
-            q = qmm[m];
-          else if (l == m + 1)
-            q = sqrt(2.0 * m + 3.0) * uz * qmm[m];
-          else
-            q = alm[l * nn + m] * (uz * q1 - blm[l * nn + m] * q2);
-          if (l > m) q2 = q1;
-          q1 = q;
-          Ybuf[(l - m) * kYStride + tid] = (float)(sc * q);
-        }
-        for (int kk = nq; kk < qpad; ++kk) Ybuf[kk * kYStride + tid] = 0.f;
-        crsh[tid] = (float)cr;
-        cish[tid] = (float)ci;
-      }
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int w = 0; w < NS; ++w) {
-        const int cs = c0 + w * kCols;
-        if (cs >= a.Npad) break;  // uniform
-        if (w == 0) {
-          // stage the first sweep's rows in LDS (the values past SR * 256 are
-          // loaded in the loop below)
+        for (int c = 0; c < NCB; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], __builtin_bit_cast(half8, bop[c][1]), acc[r][c], 0, 0,
+                                                             0);
 #pragma unroll
-          for (int u = 0; u < SR; ++u)
-            if (u * kBankPts + tid < 2 * half) Scos[u * kBankPts + tid] = sv[u];
-        } else {
-          __syncthreads();  // every wave is done with the previous sweep's rows
-        }
-        for (int idx = (w == 0 ? SR * kBankPts : 0) + tid; idx < 2 * half; idx += kBankPts) {
-          const int part = idx >= half, id2 = idx - part * half;
-          const int kr = id2 / kCols, cc = id2 - kr * kCols;
-          const bool ok = kr < nq && cs + cc < a.Npad && (m > 0 || part == 0);
-          Scos[idx] = ok ? Sm[(long long)(kr + part * nq) * a.Npad + cs + cc] : 0.f;
-        }
-        __syncthreads();
-        float crv[4], civ[4];
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          crv[r] = crsh[wave * 64 + r * 16 + (lane & 15)];
-          civ[r] = cish[wave * 64 + r * 16 + (lane & 15)];
-        }
-        const float* Sc = Scos;
-        const float* Ss = Scos + half;  // the sin rows follow the cos rows
-        // the cos rows, then (m > 0: m is uniform, a scalar branch) the sin
-        // rows, which are zero for m = 0; two loops also keep fewer steering
-        // values live than one loop over both (measured 25.9 against 26.6 ms
-        // at 256^3 x 81 rows, L = 24)
-        for (int k0 = 0; k0 < qpad; k0 += 4) {
-          const int kr = k0 + (lane >> 4);
-          float q[4], bc[CB];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) q[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
-#pragma unroll
-          for (int c = 0; c < CB; ++c) bc[c] = Sc[kr * kCols + c * 16 + (lane & 15)];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float ac = q[r] * crv[r];
-#pragma unroll
-            for (int c = 0; c < CB; ++c)
-              acc[w][r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ac, bc[c], acc[w][r][c], 0, 0, 0);
-          }
-        }
-        if (m > 0) {
-          for (int k0 = 0; k0 < qpad; k0 += 4) {
-            const int kr = k0 + (lane >> 4);
-            float q[4], bs[CB];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) q[r] = Ybuf[kr * kYStride + wave * 64 + r * 16 + (lane & 15)];
-#pragma unroll
-            for (int c = 0; c < CB; ++c) bs[c] = Ss[kr * kCols + c * 16 + (lane & 15)];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const float as = q[r] * civ[r];
-#pragma unroll
-              for (int c = 0; c < CB; ++c)
-                acc[w][r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bs[c], acc[w][r][c], 0, 0, 0);
-            }
-          }
-        }
-      }
-      __syncthreads();
+        for (int c = 0; c < NCB; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[r], __builtin_bit_cast(half8, bop[c][0]), acc[r][c], 0, 0,
+                                                             0);
     }
 
     // epilogue: psi_raw = g * h (DC: isotropic), bank rows, FP64 sums of
-    // squares and of values
+    // squares and of values.  Lane t holds column t % 16 and the four
+    // consecutive points 4 (t / 16) .. + 3 of each row block.
+    double mh[4][4];
 #pragma unroll
-    for (int w = 0; w < NS; ++w) {
-      const int cs = c0 + w * kCols;
-      if (cs >= a.Npad) break;
-      const int ncb = min(kCols, a.Npad - cs) / 16;
-      double mh[4][4];
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int i = 0; i < 4; ++i) mh[r][i] = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) mh[r][i] = 0.0;
+    for (int c = 0; c < NCB; ++c) {
+      if (c >= nact) continue;
+      const int col = (cb0 + c) * 16 + (lane & 15);
+      const bool colok = col < a.n_rows;
 #pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        if (c >= ncb) continue;
-        const int col = cs + c * 16 + (lane & 15);
-        const bool colok = col < a.n_rows;
+      for (int r = 0; r < 4; ++r) {
+        const int pt0 = wave * 64 + r * 16 + 4 * (lane >> 4);
+        float vv[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int i = 0; i < 4; ++i) {
+          const int pt = pt0 + i;
+          const int fl = flags[pt];
+          const double h = (fl & 1) ? a.dc_value : (double)(acc[r][c][i] * a.out_scale);
+          const float v = (float)(gsh[pt] * h);
+          vv[i] = v;
+          if (colok) {
+            mh[r][i] += (double)v * (double)v;
+            if (fl & 2) asum += (double)v;
+          }
+        }
+        if (colok) {
+          float* dst = a.psi + (long long)col * a.V + p0 + pt0;
+          if (vec_store) {
+            *(float4*)dst = float4{vv[0], vv[1], vv[2], vv[3]};
+          } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int pt = wave * 64 + r * 16 + 4 * (lane >> 4) + i;
-            const long long gp = p0 + pt;
-            double h = dcsh[pt] ? a.dc_value : (double)acc[w][r][c][i];
-            float v = (float)(gsh[pt] * h);
-            if (colok && gp < a.V) a.psi[(long long)col * a.V + gp] = v;
-            if (colok) {
-              mh[r][i] += (double)v * (double)v;
-              if (bandsh[pt]) asum += (double)v;
-            }
+            for (int i = 0; i < 4; ++i)
+              if (p0 + pt0 + i < a.V) dst[i] = vv[i];
           }
         }
       }
-      // sum over the 16 lanes that share (lane >> 4): fixed xor tree, then
-      // into the point's running sum (one owner lane per point)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          double s = mh[r][i];
-          s += __shfl_xor(s, 1);
-          s += __shfl_xor(s, 2);
-          s += __shfl_xor(s, 4);
-          s += __shfl_xor(s, 8);
-          if ((lane & 15) == 0) Msh[wave * 64 + r * 16 + 4 * (lane >> 4) + i] += s;
-        }
     }
+    // sum over the 16 lanes that share (lane >> 4): fixed xor tree, then
+    // into the point's running sum (one owner lane per point)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double s = mh[r][i];
+        s += __shfl_xor(s, 1);
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 4);
+        s += __shfl_xor(s, 8);
+        if ((lane & 15) == 0) Msh[wave * 64 + r * 16 + 4 * (lane >> 4) + i] += s;
+      }
   }
   __syncthreads();
   const double mt = Msh[tid];
   if (valid) a.Mh[p] = mt;
-  // the workgroup's band sums, by a fixed tree (deterministic); Msh and
-  // Ash are reused as the tree's buffers
-  double cnt = band ? 1.0 : 0.0;
-  double ms = band ? mt : 0.0, as = asum;
-  __syncthreads();
-  Msh[tid] = ms;
-  Ash[tid] = as;
-  gsh[tid] = cnt;
+  // the workgroup's band sums, by a fixed tree (deterministic), in the ring's
+  // memory
+  double* tm = (double*)&ring[0][0][0];
+  double* ta = tm + kBankPts;
+  double* tc = ta + kBankPts;
+  tm[tid] = band ? mt : 0.0;
+  ta[tid] = asum;
+  tc[tid] = band ? 1.0 : 0.0;
   __syncthreads();
   for (int w = kBankPts / 2; w > 0; w >>= 1) {
     if (tid < w) {
-      Msh[tid] += Msh[tid + w];
-      Ash[tid] += Ash[tid + w];
-      gsh[tid] += gsh[tid + w];
+      tm[tid] += tm[tid + w];
+      ta[tid] += ta[tid + w];
+      tc[tid] += tc[tid + w];
     }
     __syncthreads();
   }
   if (tid == 0) {
-    a.part[3 * (long long)blockIdx.x] = Msh[0];
-    a.part[3 * (long long)blockIdx.x + 1] = Ash[0];
-    a.part[3 * (long long)blockIdx.x + 2] = gsh[0];
+    a.part[3 * (long long)blockIdx.x] = tm[0];
+    a.part[3 * (long long)blockIdx.x + 1] = ta[0];
+    a.part[3 * (long long)blockIdx.x + 2] = tc[0];
   }
 }
 
@@ -480,41 +489,32 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   a.Nx = (int)b->dims[2];
   a.V = b->V;
   a.L = L;
-  a.Npad = b->Npad;
   a.n_rows = b->n_unique;
   const double rhoN = 3.14159265358979323846;
   const double t = 2.0 * (b->params.gamma * rhoN) * (b->params.gamma * rhoN) / (1.0 + 2.0 * b->params.taylor_N);
   a.t_inv = 1.0 / t;
   a.taylor_N = b->params.taylor_N;
-  a.S = b->d.S;
+  a.S = (const uint4*)b->d.S;
   a.tab = b->d.tab;
-  a.koff = (const int*)(b->d.tab + nn + 2 * nn * nn);
   a.psi = b->d.psi;
   a.Mh = b->d.Mh;
   a.part = b->d.part;
   a.dc_value = b->dc_value;
-  // LDS rows per chunk: the L + 1 - m values Q_l^m, padded to 4 (largest at m = 0)
-  const int maxpad = (nn + 3) / 4 * 4;
-  a.maxpad = maxpad;
+  a.ncb = b->Npad / 16;
+  a.kblocks = b->kblocks;
+  a.out_scale = b->synth_scale;
   const long long nblk = (b->V + kBankPts - 1) / kBankPts;
-  // the stored rows in one sweep of 32 or 48 columns, or two 48-column
-  // sweeps per recursion
-  const int cb = (b->Npad <= 32) ? 2 : 3;
-  const int ns = (b->Npad > kColsPerSweep) ? 2 : 1;
-  size_t lds = (size_t)maxpad * (kYStride + 2 * 16 * cb) * sizeof(float);
-  const void* kfn = ns == 2 ? (const void*)k_bank_synth<2, 3>
-                            : (cb == 2 ? (const void*)k_bank_synth<1, 2> : (const void*)k_bank_synth<1, 3>);
-  if (hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
-    set_error("k_bank_synth: cannot reserve LDS");
-    return OS3D_EDEVICE;
-  }
   void* tok = prof_start(st, PROF_BANK);
-  if (ns == 2)
-    launch_k(k_bank_synth<2, 3>, dim3((unsigned)nblk), dim3(256), lds, st, a);
-  else if (cb == 2)
-    launch_k(k_bank_synth<1, 2>, dim3((unsigned)nblk), dim3(256), lds, st, a);
-  else
-    launch_k(k_bank_synth<1, 3>, dim3((unsigned)nblk), dim3(256), lds, st, a);
+  // 16-column blocks per sweep: at most kMaxNcb, the sweeps evenly filled
+  const int sweeps = (a.ncb + kMaxNcb - 1) / kMaxNcb;
+  switch ((a.ncb + sweeps - 1) / sweeps) {
+    case 1: launch_k(k_bank_synth<1>, dim3((unsigned)nblk), dim3(256), 0, st, a); break;
+    case 2: launch_k(k_bank_synth<2>, dim3((unsigned)nblk), dim3(256), 0, st, a); break;
+    case 3: launch_k(k_bank_synth<3>, dim3((unsigned)nblk), dim3(256), 0, st, a); break;
+    case 4: launch_k(k_bank_synth<4>, dim3((unsigned)nblk), dim3(256), 0, st, a); break;
+    case 5: launch_k(k_bank_synth<5>, dim3((unsigned)nblk), dim3(256), 0, st, a); break;
+    default: launch_k(k_bank_synth<6>, dim3((unsigned)nblk), dim3(256), 0, st, a); break;
+  }
   // algorithmic work of the contraction: 2 V (L+1)^2 n_rows flops
   prof_stop(tok, st, PROF_BANK, 0.0, 2.0 * (double)b->V * (double)(nn * nn) * (double)b->n_unique);
   int rc = check_launch("k_bank_synth");

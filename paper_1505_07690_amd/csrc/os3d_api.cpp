@@ -97,7 +97,6 @@ static BankLayout layout(const int64_t dims[3], int n_unique, int L) {
   const size_t V = (size_t)dims[0] * dims[1] * dims[2];
   const int nn = L + 1;
   const int Npad = (n_unique + 15) / 16 * 16;
-  const KLayout kl = k_layout(L);
   size_t o = 0;
   b.psi = o;
   o = align256(o + (size_t)n_unique * V * sizeof(float));
@@ -106,9 +105,9 @@ static BankLayout layout(const int64_t dims[3], int n_unique, int L) {
   b.Mh = o;
   o = align256(o + V * sizeof(double));
   b.S = o;
-  o = align256(o + (size_t)kl.K * Npad * sizeof(float));
+  o = align256(o + (size_t)synth_kblocks(L) * (Npad / 16) * 2 * 64 * 16);
   b.tab = o;
-  o = align256(o + (size_t)(nn + 2 * nn * nn + nn) * sizeof(double));
+  o = align256(o + (size_t)4 * (2 * ((L + 2) / 2) + L * nn / 2) * sizeof(double));
   b.part = o;  // band partials of the synthesis workgroups (3 each), then kappa and S
   o = align256(o + (3 * ((V + 255) / 256) + 2) * sizeof(double));
   for (int d = 0; d < 3; ++d) {
@@ -205,7 +204,7 @@ os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_
   b->d.psi = (float*)(base + lay.psi);
   b->d.M = (float*)(base + lay.M);
   b->d.Mh = (double*)(base + lay.Mh);
-  b->d.S = (float*)(base + lay.S);
+  b->d.S = (uint32_t*)(base + lay.S);
   b->d.tab = (double*)(base + lay.tab);
   b->d.part = (double*)(base + lay.part);
   for (int d = 0; d < 3; ++d) b->d.tw[d] = (float*)(base + lay.tw[d]);
@@ -216,35 +215,76 @@ os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_
     for (int s = 0; s < kMaxStages; ++s) b->plan[d].radix[s] = s < (int)r.size() ? r[s] : 0;
   }
 
-  // host FP64 design: coefficients, steering matrix in K-layout, recursion tables, twiddles
+  // host FP64 design: coefficients, steering matrix as MFMA operands, recursion tables, twiddles
   std::vector<double> c, a;
   wavelet_coeffs(*p, c, a);
   b->dc_value = a[0] / std::sqrt(4.0 * 3.14159265358979323846);
   const int L = p->L, nn = L + 1;
-  const KLayout kl = k_layout(L);
-  b->K = kl.K;
   std::vector<double> Sstd((size_t)nn * nn * b->n_unique);
   std::vector<double> rep_or(3 * b->n_unique);
   for (int r = 0; r < b->n_unique; ++r)
     for (int c3 = 0; c3 < 3; ++c3) rep_or[3 * r + c3] = orients[3 * b->rep[r] + c3];
   steering_std(*p, rep_or.data(), b->n_unique, a, Sstd.data());
-  std::vector<float> S((size_t)kl.K * b->Npad, 0.f);
-  for (int l = 0; l <= L; ++l)
-    for (int m = -l; m <= l; ++m) {
-      const int k = (m == 0) ? k_index(kl, l, 0, false) : k_index(kl, l, std::abs(m), m < 0);
-      for (int r = 0; r < b->n_unique; ++r)
-        S[(size_t)k * b->Npad + r] = (float)Sstd[(size_t)(l * l + l + m) * b->n_unique + r];
-    }
+  // fp16 hi / lo operands: S 2^e_S = hi + lo, e_S putting max |S| in
+  // [2^14, 2^15) (fp16 holds up to 65504); the device scales Y_lm by 2^13
+  // and the product back by synth_scale = 2^-(13 + e_S)
+  double smax = 0.0;
+  for (double v : Sstd) smax = std::max(smax, std::fabs(v));
+  const int eS = smax > 0.0 ? 14 - (int)std::floor(std::log2(smax)) : 0;
+  b->synth_scale = (float)std::ldexp(1.0, -(13 + eS));
+  b->kblocks = synth_kblocks(L);
+  const int ncb = b->Npad / 16;
+  // operand order of v_mfma_f32_16x16x32_f16's B: lane t holds column t % 16
+  // and the eight K entries 8 (t / 16) .. + 7, two per word (low half first)
+  std::vector<uint32_t> S((size_t)b->kblocks * ncb * 2 * 64 * 4, 0u);
+  for (int kb = 0; kb < b->kblocks; ++kb)
+    for (int cb = 0; cb < ncb; ++cb)
+      for (int t = 0; t < 64; ++t) {
+        const int col = cb * 16 + (t & 15);
+        for (int j = 0; j < 8; ++j) {
+          int l, m;
+          bool sn;
+          float v = 0.f;
+          if (col < b->n_unique && synth_entry(L, kb * 32 + 8 * (t >> 4) + j, l, m, sn)) {
+            const int idx = l * l + l + (sn ? -m : m);
+            v = (float)std::ldexp(Sstd[(size_t)idx * b->n_unique + col], eS);
+          }
+          const _Float16 hi = (_Float16)v;
+          const _Float16 lo = (_Float16)(v - (float)hi);
+          uint16_t hb, lb;
+          std::memcpy(&hb, &hi, 2);
+          std::memcpy(&lb, &lo, 2);
+          const size_t w = ((((size_t)kb * ncb + cb) * 2) * 64 + t) * 4 + j / 2;
+          const int sh = (j & 1) * 16;
+          S[w] |= (uint32_t)hb << sh;
+          S[w + 64 * 4] |= (uint32_t)lb << sh;
+        }
+      }
   ShTables t = sh_tables(L);
-  std::vector<double> tab(nn + 2 * nn * nn + nn, 0.0);
-  std::copy(t.qmm.begin(), t.qmm.end(), tab.begin());
-  std::copy(t.alm.begin(), t.alm.end(), tab.begin() + nn);
-  std::copy(t.blm.begin(), t.blm.end(), tab.begin() + nn + nn * nn);
-  int* ko = (int*)(tab.data() + nn + 2 * nn * nn);
-  for (int m = 0; m <= L; ++m) {
-    ko[m] = kl.off[m];
-    ko[nn + m] = kl.pad[m];
-  }
+  // the recursion steps in the synthesis order (Q = alpha (z Q' - beta Q'')
+  // + gamma, a flag where an order m >= 1 starts): m = 0 in 2 ((L + 2) / 2)
+  // steps (the last one zero when L is even), then l = m..L for m = 1..L
+  const int w0 = (L + 2) / 2;
+  std::vector<double> tab((size_t)4 * (2 * w0 + L * nn / 2), 0.0);
+  auto put_step = [&](int s, int l, int m) {
+    double* r = &tab[(size_t)4 * s];
+    if (l == m) {
+      r[2] = t.qmm[m];
+      if (m > 0) {
+        const long long one = 1;
+        std::memcpy(&r[3], &one, sizeof one);
+      }
+    } else if (l == m + 1) {
+      r[0] = std::sqrt(2.0 * m + 3.0);
+    } else {
+      r[0] = t.alm[l * nn + m];
+      r[1] = t.blm[l * nn + m];
+    }
+  };
+  for (int l = 0; l <= L; ++l) put_step(l, l, 0);
+  int step = 2 * w0;
+  for (int m = 1; m <= L; ++m)
+    for (int l = m; l <= L; ++l) put_step(step++, l, m);
   std::vector<float> tw[3];
   for (int d = 0; d < 3; ++d) {
     const int N = (int)dims[d];
@@ -256,7 +296,7 @@ os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_
     }
   }
   hipStream_t st = (hipStream_t)stream;
-  bool ok = hipMemcpyAsync(b->d.S, S.data(), S.size() * sizeof(float), hipMemcpyHostToDevice, st) == hipSuccess &&
+  bool ok = hipMemcpyAsync(b->d.S, S.data(), S.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st) == hipSuccess &&
             hipMemcpyAsync(b->d.tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, st) == hipSuccess;
   for (int d = 0; d < 3 && ok; ++d)
     ok = hipMemcpyAsync(b->d.tw[d], tw[d].data(), tw[d].size() * sizeof(float), hipMemcpyHostToDevice, st) ==

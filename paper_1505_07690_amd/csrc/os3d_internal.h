@@ -10,8 +10,8 @@
 
 namespace os3d {
 
-// Largest SH order of the device bank synthesis: its LDS holds the largest
-// K-chunk (2L values, padded to 4) for 256 points plus the staged steering rows.
+// Largest SH order of the device bank synthesis (its fp16 operands hold
+// |Y_lm| <= sqrt((2L + 1) / 4 pi) scaled by 2^13).
 constexpr int kMaxBankL = 62;
 
 constexpr int kMaxL = 64;
@@ -39,18 +39,13 @@ struct ShTables {
 ShTables sh_tables(int L);
 void real_sh(const ShTables& t, const double n[3], double* Y);  // index l*l + l + m
 
-// Layout of the contraction dimension K used by the bank kernel: chunks by m
-// (m = 0: l = 0..L; m >= 1: cos terms l = m..L, then sin terms l = m..L),
-// each chunk padded to a multiple of 4 rows.
-struct KLayout {
-  int L;
-  int K;                    // padded total
-  std::vector<int> off;     // chunk start, m = 0..L
-  std::vector<int> len;     // unpadded chunk length
-  std::vector<int> pad;     // padded chunk length
-};
-KLayout k_layout(int L);
-int k_index(const KLayout& kl, int l, int m, bool sin_part);
+// Contraction order (K) of the bank synthesis: m = 0 with l = 0..L (padded
+// to an even count), then for m = 1..L and l = m..L the pair (cos, sin).
+// Two consecutive entries share one 32-bit word of fp16 values; 16 words
+// (32 entries) are one K-block of the 16x16x32 fp16 MFMA.
+int synth_words(int L);                                        // (L + 2) / 2 + L (L + 1) / 2
+int synth_kblocks(int L);                                      // ceil(words / 16)
+bool synth_entry(int L, int e, int& l, int& m, bool& sin_part);  // false for padding
 
 void steering_std(const os3d_wavelet_params& p, const double* orients, int n, const std::vector<double>& a,
                   double* S);  // [(L+1)^2][n], standard order
@@ -72,8 +67,8 @@ struct DevPtrs {
   float* psi;      // [n_unique][V] float32 g h without kappa (the transforms apply kappa)
   float* M;        // [V]
   double* Mh;      // [V] FP64 sum over stored rows of raw psi^2 (build scratch)
-  float* S;        // [K][Npad] steering matrix in K-layout
-  double* tab;     // recursion tables: qmm[L+1], alm[(L+1)^2], blm[(L+1)^2], sqrt(2m+3)[L+1]
+  uint32_t* S;     // steering matrix as fp16 hi / lo MFMA operands: [kblocks][Npad / 16][2][64][4 words]
+  double* tab;     // recursion steps of the synthesis: [steps][alpha, beta, gamma, order-start flag]
   double* part;    // band partials of the synthesis, then kappa and S
   float* tw[3];    // twiddles exp(-2 pi i j / N_d), j < N_d, per axis (z, y, x)
 };
@@ -90,7 +85,8 @@ struct os3d_bank {
   int plane;                  // natural order with Ny = Nx in {64, 128}: z-line pass + whole-plane pass
   int L;
   int Npad;
-  int K;
+  int kblocks;                // K-blocks of the synthesis contraction
+  float synth_scale;          // 2^-(13 + e_S): undoes the fp16 operand scaling
   double kappa;
   double dc_value;            // a_0 / sqrt(4 pi): the sphere average of h, used at k = 0
   double approx_norm;         // band mean of sum_i psi_hat_i (approximate reconstruction)

@@ -55,21 +55,38 @@ int main() {
     if (prod != len || (int)r.size() > kMaxStages) ++bad;
     ++plans;
   }
-  // the contraction layout of the bank kernel addresses every (l, m) once
+  // the contraction order of the bank kernel addresses every (l, m, cos / sin)
+  // once, within its K-blocks, and the device's generation order (m = 0 in
+  // pairs of l, then one (cos, sin) word per l) gives the same word indices
   for (int L : Ls) {
-    KLayout kl = k_layout(L);
-    std::vector<int> seen(kl.K, 0);
-    for (int l = 0; l <= L; ++l)
-      for (int m = 0; m <= l; ++m) {
-        ++seen[k_index(kl, l, m, false)];
-        if (m > 0) ++seen[k_index(kl, l, m, true)];
-      }
+    const int ne = 32 * synth_kblocks(L);
+    if (ne < 2 * synth_words(L) || ne >= 2 * synth_words(L) + 32) ++bad;
+    std::vector<int> seen((size_t)(L + 1) * (L + 1) * 2, 0);
     int used = 0;
-    for (int v : seen) {
-      if (v > 1) ++bad;
-      used += v;
+    for (int e = 0; e < ne; ++e) {
+      int l, m;
+      bool sn;
+      if (!synth_entry(L, e, l, m, sn)) continue;
+      if (l < m || l > L || (m == 0 && sn)) ++bad;
+      ++seen[(size_t)(l * (L + 1) + m) * 2 + (sn ? 1 : 0)];
+      ++used;
     }
+    for (int v : seen)
+      if (v > 1) ++bad;
     if (used != (L + 1) * (L + 1)) ++bad;
+    int w = 0;
+    for (int l = 0; l <= L; l += 2, ++w) {
+      int l2, m2;
+      bool s2;
+      if (!synth_entry(L, 2 * w, l2, m2, s2) || l2 != l || m2 != 0) ++bad;
+    }
+    for (int m = 1; m <= L; ++m)
+      for (int l = m; l <= L; ++l, ++w) {
+        int l2, m2;
+        bool s2;
+        if (!synth_entry(L, 2 * w + 1, l2, m2, s2) || l2 != l || m2 != m || !s2) ++bad;
+      }
+    if (w != synth_words(L)) ++bad;
   }
   std::printf("plans %d bad %d\n", plans, bad);
   return bad ? 1 : 0;

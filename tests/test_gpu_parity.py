@@ -86,14 +86,19 @@ CASES = {
                    inputs.tubes((10, 12, 8), 2, 1.2, 0.1, 0, 20)),
     "single": lambda: ((12, 8, 10), np.array([[0.0, 0.0, 1.0]]), _oracle_params(8, 12),
                        inputs.tubes((12, 8, 10), 2, 1.2, 0.1, 0, 21)),
-    # more than 48 stored rows: two 48-column sweeps per recursion in the bank
-    # synthesis (81 rows of the 162-orientation set; 60 unpaired rows, the
-    # second sweep partly filled)
+    # the bank synthesis takes the stored rows in 16-column blocks, up to six
+    # per sweep of its recursion, the sweeps evenly filled: 81 rows of the
+    # 162-orientation set (six blocks, the last one partly filled), 60, 70
+    # and 40 unpaired rows (four, five and three blocks), 110 unpaired rows
+    # (two sweeps of four blocks, the second one partly filled)
     "ico162": lambda: ((10, 12, 8), inputs.icosahedral_orientations(2), _oracle_params(12, 162),
                        inputs.tubes((10, 12, 8), 2, 1.2, 0.1, 0, 22)),
     "rand60": lambda: ((8, 10, 12), _random_orients(60, 23), _oracle_params(8, 60),
                        inputs.tubes((8, 10, 12), 2, 1.2, 0.1, 0, 24)),
-    # 33-48 stored rows: one 48-column sweep (up to 32 rows take a 32-column sweep)
+    "rand70": lambda: ((9, 8, 10), _random_orients(70, 29), _oracle_params(10, 70),
+                       inputs.tubes((9, 8, 10), 2, 1.2, 0.1, 0, 30)),
+    "rand110": lambda: ((8, 10, 12), _random_orients(110, 31), _oracle_params(6, 110),
+                        inputs.tubes((8, 10, 12), 2, 1.2, 0.1, 0, 32)),
     "rand40": lambda: ((10, 8, 12), _random_orients(40, 25), _oracle_params(10, 40),
                        inputs.tubes((10, 8, 12), 2, 1.2, 0.1, 0, 26)),
     # the two non-power-of-two shapes of the serving workload (12 orientations
@@ -127,7 +132,8 @@ def test_bank_and_M_parity(case):
     assert rel(psi, ob["psi_hat"]) < TOL
     assert rel(gb.M().cpu().numpy(), ob["M"]) < TOL
     assert abs(gb.kappa - ob["kappa"]) < 1e-6 * ob["kappa"]
-    assert gb.paired == (case["name"] not in ("unpaired_plate", "tetra", "single", "rand60", "rand40"))
+    unpaired = ("unpaired_plate", "tetra", "single", "rand60", "rand40", "rand70", "rand110")
+    assert gb.paired == (case["name"] not in unpaired)
 
 
 def test_forward_parity(case):
