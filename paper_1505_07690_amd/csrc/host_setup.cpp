@@ -275,30 +275,74 @@ void real_sh(const ShTables& t, const double n[3], double* Y) {
   }
 }
 
-int synth_words(int L) { return (L + 2) / 2 + L * (L + 1) / 2; }
+// Words of orders m0..m1 (one per (l, m), l = m..L).
+static int order_words(int L, int m0, int m1) {
+  int n = 0;
+  for (int m = m0; m <= m1; ++m) n += L + 1 - m;
+  return n;
+}
+
+int synth_split(int L) {
+  int best = L, best_len = order_words(L, 0, L);
+  for (int M = 0; M <= L; ++M) {
+    const int len = std::max(order_words(L, 0, M), order_words(L, M + 1, L));
+    if (len < best_len) {
+      best_len = len;
+      best = M;
+    }
+  }
+  return best;
+}
+
+int synth_pairs(int L) {
+  const int M = synth_split(L);
+  return std::max(order_words(L, 0, M), order_words(L, M + 1, L));
+}
+
+int synth_words(int L) { return 2 * synth_pairs(L); }
 
 int synth_kblocks(int L) { return (synth_words(L) + 15) / 16; }
 
-bool synth_entry(int L, int e, int& l, int& m, bool& sin_part) {
-  const int w = e >> 1, h = e & 1;
-  const int w0 = (L + 2) / 2;
-  sin_part = false;
-  if (w < w0) {  // m = 0: two consecutive l per word
-    m = 0;
-    l = 2 * w + h;
-    return l <= L;
-  }
-  int r = w - w0;
-  for (m = 1; m <= L; ++m) {  // one l per word: (cos, sin)
+int synth_sweep_blocks(int ncb) {
+  const int sweeps = (ncb + kSynthMaxBlocks - 1) / kSynthMaxBlocks;
+  return (ncb + sweeps - 1) / sweeps;
+}
+
+int synth_padded_blocks(int ncb) {
+  const int per = synth_sweep_blocks(ncb);
+  return (ncb + per - 1) / per * per;
+}
+
+// The i-th step of a chain over orders m0..m1: (l, m), false past its end.
+static bool chain_step(int L, int m0, int m1, int i, int& l, int& m) {
+  for (m = m0; m <= m1; ++m) {
     const int n = L + 1 - m;
-    if (r < n) {
-      l = m + r;
-      sin_part = (h == 1);
+    if (i < n) {
+      l = m + i;
       return true;
     }
-    r -= n;
+    i -= n;
   }
   return false;
+}
+
+bool synth_entry(int L, int e, int& l, int& m, bool& sin_part) {
+  const int w = e >> 1, i = w >> 1;
+  sin_part = (e & 1) == 1;
+  const int M = synth_split(L);
+  const bool ok = (w & 1) == 0 ? chain_step(L, 0, M, i, l, m) : chain_step(L, M + 1, L, i, l, m);
+  return ok && !(m == 0 && sin_part);
+}
+
+std::vector<int> synth_word_order(int L) {
+  const int M = synth_split(L);
+  std::vector<int> lm((size_t)16 * synth_kblocks(L), -1);
+  for (int chain = 0; chain < 2; ++chain) {
+    int i = 0;
+    for (int m = chain == 0 ? 0 : M + 1; m <= (chain == 0 ? M : L); ++m)
+      for (int l = m; l <= L; ++l, ++i) lm[(size_t)2 * i + chain] = l * (L + 1) + m;
+  }
+  return lm;
 }
 
 void steering_std(const os3d_wavelet_params& p, const double* orients, int n, const std::vector<double>& a,

@@ -14,15 +14,15 @@
 // by 2^-(13 + e_S).
 //
 // Each wave owns 64 frequency points and works alone: every lane runs the
-// FP64 normalised recursion for its point's Q_l^m, one K entry pair per
-// step, multiplies by Re / Im (x + iy)^m (the sinus power is in that
-// factor), splits into hi / lo and writes the pair to the wave's LDS ring
-// (two K-blocks of 32 entries, [word][point]).  When a K-block is complete
-// the wave reads it back in the MFMA's A-operand order (lane t: point t % 16
-// of each 16-point row block, entries 8 (t / 16) .. + 7) and runs the block
-// against the steering operands, which the host packed in the B-operand
-// order and which the wave loads from memory (L2-resident) while it
-// generates the block.  The epilogue multiplies by the FP64 radial window
+// FP64 normalised recursion for its point's Q_l^m, one K entry pair (cos,
+// sin) per step, multiplies by Re / Im (x + iy)^m (the sinus power is in
+// that factor), splits into hi / lo and writes the word to the wave's LDS
+// ring (one K-block, [word pair][point][2 words]).  When the K-block is
+// complete the wave reads it back in the MFMA's A-operand order (lane t:
+// point t % 16 of each 16-point row block, entries 8 (t / 16) .. + 7) and
+// runs the block against the steering operands, which the host packed in
+// the B-operand order and which the wave loads from memory (L2-resident)
+// while it generates the block.  The epilogue multiplies by the FP64 radial window
 // g(rho) (Eq. 10), applies the Nyquist and DC rules, writes the bank rows
 // and accumulates sum_i psi_i^2 (Eq. 9) and sum_i psi_i in FP64 with a
 // fixed-order cross-lane tree; the workgroup's sums of both over the
@@ -47,9 +47,8 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __fp16 fp16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kBankPts = 256;    // frequency points per workgroup (four independent waves)
-constexpr int kRingRows = 32;    // two K-blocks of 16 words
-constexpr int kRingStride = 68;  // words per ring row: rows 4 apart fall 16 banks apart (A reads conflict-free)
-constexpr int kMaxNcb = 6;       // 16-column blocks per sweep
+constexpr int kRingRows = 8;     // word pairs of one K-block
+constexpr int kRingStride = 144; // words per ring row (64 points x 2 words + 16): rows 2 apart fall 32 banks apart
 constexpr double kYScale = 8192.0;  // 2^13
 
 struct BankArgs {
@@ -57,12 +56,13 @@ struct BankArgs {
   int Nz, Ny, Nx;
   long long V;
   int L, n_rows, ncb, kblocks;
+  int mb;             // first order of recursion chain B
   double t_inv;       // 1 / t of Eq. (10)
   int taylor_N;
   double dc_value;    // a_0 / sqrt(4 pi)
   float out_scale;    // 2^-(13 + e_S)
-  const uint4* S;     // [kblocks][ncb][2 (hi, lo)][64 lanes] B operands
-  const double* tab;  // recursion steps [steps][alpha, beta, gamma, order-start flag]
+  const uint4* S;     // [kblocks][ncb][2 (hi, lo)][64 lanes] B operands, ncb a multiple of the sweep's
+  const double* tab;  // recursion steps [kblocks * 8][chain A, B][c0, c1], then order-start masks
   float* psi;         // [n_rows][V]
   double* Mh;         // [V]
   double* part;       // [gridDim.x][3]: band sums of Mh and of sum_i psi_i, band count
@@ -86,28 +86,60 @@ __device__ inline double radial_g(double rho2, double t_inv, int N) {
   return acc;
 }
 
-// fp16 hi / lo parts of two values (round to nearest even both times),
-// packed low half first.
-__device__ __forceinline__ void split_pair(float u, float v, unsigned& hi, unsigned& lo) {
-  const _Float16 hu = (_Float16)u, hv = (_Float16)v;
-  const _Float16 lu = (_Float16)(u - (float)hu), lv = (_Float16)(v - (float)hv);
-  hi = (unsigned)__builtin_bit_cast(unsigned short, hu) | ((unsigned)__builtin_bit_cast(unsigned short, hv) << 16);
-  lo = (unsigned)__builtin_bit_cast(unsigned short, lu) | ((unsigned)__builtin_bit_cast(unsigned short, lv) << 16);
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+// fp16 hi / lo parts of q c and q s (round to nearest even), packed low
+// half first.  The products are rounded to FP32 once and held in registers
+// (the empty asm): otherwise the compiler may fuse a product into the fp16
+// conversion on one path and not on the other, and the hi part in the word
+// would differ from the one the residual subtracts (hi + lo then misses q c
+// by an fp16 ulp).  The residual subtracts the packed hi values themselves.
+__device__ __forceinline__ void split_pair(float q, float c, float s, unsigned& hi, unsigned& lo) {
+  float u = q * c, v = q * s;
+  asm volatile("" : "+v"(u), "+v"(v));
+  half2v h;
+  h.x = (_Float16)u;
+  h.y = (_Float16)v;
+  hi = __builtin_bit_cast(unsigned, h);
+  asm volatile("" : "+v"(hi));  // unpack the packed word (no second conversion)
+  const half2v hh = __builtin_bit_cast(half2v, hi);
+  half2v l;
+  l.x = (_Float16)(u - (float)hh.x);
+  l.y = (_Float16)(v - (float)hh.y);
+  lo = __builtin_bit_cast(unsigned, l);
 }
 
-// The recursion steps in the synthesis order, one record of four doubles
-// per step: Q = alpha (z Q' - beta Q'') + gamma (Q', Q'': the two previous
-// values of the order), and a nonzero fourth word where an order m >= 1
-// starts.  m = 0 takes two steps per word (the last one zero when L is
-// even), every later order one step per word.  The table is read-only
-// during the synthesis: read through the constant address space, its
-// uniform records become scalar loads, which do not wait behind the vector
-// loads of the steering operands.
-typedef const double __attribute__((address_space(4)))* ctab_t;
-typedef const long long __attribute__((address_space(4)))* cflag_t;
+// The recursion runs as two independent chains, A over the orders 0..M and
+// B over M + 1..L, which fill the even and odd words of the K order: two
+// dependency chains in flight per lane.  Per word pair the table holds one
+// record (c0, c1) per chain, Q = c0 (z Q') - c1 Q'' (Q', Q'': the chain's
+// two previous values): inside an order c0 = alpha_lm and c1 = alpha_lm
+// beta_lm of the normalised recursion; where an order starts c0 = 0 and
+// c1 = -Q_m^m, and the chain sets Q'' = 1 first; zero records past a
+// chain's end.  After the records, one 32-bit mask per K-block marks the
+// pairs that start an order (bit i: chain A, bit 8 + i: chain B).  The
+// table is read-only during the synthesis: read through the constant
+// address space, the uniform records become scalar loads (one per pair) and
+// the masks scalar bit tests, which do not wait behind the vector loads of
+// the steering operands.
+struct StepPair {
+  double a[2], b[2];  // chain A, chain B: c0, c1
+};
+typedef const StepPair __attribute__((address_space(4)))* ctab_t;
+typedef const unsigned __attribute__((address_space(4)))* cmask_t;
 
-__device__ __forceinline__ double rec_step(ctab_t r, double uz, double& q1, double& q2) {
-  const double q = fma(r[0], fma(uz, q1, -r[1] * q2), r[2]);
+__device__ __forceinline__ StepPair load_steps(ctab_t p) {
+  StepPair r;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    r.a[j] = p->a[j];
+    r.b[j] = p->b[j];
+  }
+  return r;
+}
+
+__device__ __forceinline__ double rec_step(const double* r, double uz, double& q1, double& q2) {
+  const double q = fma(r[0], uz * q1, -(r[1] * q2));
   q2 = q1;
   q1 = q;
   return q;
@@ -127,8 +159,7 @@ __global__ __launch_bounds__(256, 2) void k_bank_synth(BankArgs a) {
   const bool valid = p < a.V;
   const int L = a.L;
   const ctab_t tab = (ctab_t)a.tab;
-  const int w0 = (L + 2) / 2;              // words of order m = 0
-  const int nwords = w0 + L * (L + 1) / 2;
+  const cmask_t starts = (cmask_t)(tab + a.kblocks * 8);  // after the records
   unsigned* hiP = ring[wave][0];
   unsigned* loP = ring[wave][1];
 
@@ -165,16 +196,23 @@ __global__ __launch_bounds__(256, 2) void k_bank_synth(BankArgs a) {
 
   const bool vec_store = (a.V % 4 == 0) && (pw + 64 <= a.V);
   for (int cb0 = 0; cb0 < a.ncb; cb0 += NCB) {
-    const int nact = min(NCB, a.ncb - cb0);  // uniform
     floatx4 acc[4][NCB];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int c = 0; c < NCB; ++c) acc[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    double q1 = 0.0, q2 = 0.0;        // the recursion's two previous values
-    double cr = 1.0, ci = 0.0;        // (x + iy)^m
-    float crs = 0.f, cis = 0.f;       // (x + iy)^m times sqrt 2 and 2^13, in FP32
+    // chain A starts at m = 0 ((x + iy)^0 = 1, no sqrt 2), chain B at m = mb
+    const double sc = 1.4142135623730950488 * kYScale;
+    double qa1 = 0.0, qa2 = 0.0, qb1 = 0.0, qb2 = 0.0;  // the chains' two previous values
+    double cra = 1.0, cia = 0.0, crb = 1.0, cib = 0.0;  // (x + iy)^m of each chain
+    for (int m = 0; m < a.mb; ++m) {
+      const double nr = crb * ux - cib * uy, ni = crb * uy + cib * ux;
+      crb = nr;
+      cib = ni;
+    }
+    float crsa = (float)kYScale, cisa = 0.f;  // times sqrt 2 (m > 0) and 2^13, in FP32
+    float crsb = (float)(crb * sc), cisb = (float)(cib * sc);
     for (int kb = 0; kb < a.kblocks; ++kb) {
       // the block's steering operands: in flight while the block is generated
       uint4 bop[NCB][2];
@@ -182,58 +220,62 @@ __global__ __launch_bounds__(256, 2) void k_bank_synth(BankArgs a) {
       for (int c = 0; c < NCB; ++c)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
-          bop[c][h] = (c < nact) ? a.S[(((long long)kb * a.ncb + cb0 + c) * 2 + h) * 64 + lane]
-                                 : uint4{0u, 0u, 0u, 0u};
-      // generate the block's 16 words (uniform control flow)
-      const int rb = (kb & 1) * 16;
-#pragma unroll 2
-      for (int w = 0; w < 16; ++w) {
-        const int gw = kb * 16 + w;
-        float u = 0.f, v = 0.f;
-        if (gw < w0) {  // m = 0: two consecutive l per word
-          const ctab_t r = tab + 8 * gw;
-          u = (float)(rec_step(r, uz, q1, q2) * kYScale);
-          v = (float)(rec_step(r + 4, uz, q1, q2) * kYScale);
-        } else if (gw < nwords) {  // one l per word: cos and sin parts
-          const int st = w0 + gw;  // 2 w0 steps of m = 0 before
-          if (((cflag_t)tab)[4 * st + 3] != 0) {  // order m starts: (x + iy)^m
-            const double nr = cr * ux - ci * uy, ni = cr * uy + ci * ux;
-            cr = nr;
-            ci = ni;
-            const double sc = 1.4142135623730950488 * kYScale;
-            crs = (float)(nr * sc);
-            cis = (float)(ni * sc);
+          bop[c][h] = a.S[(((long long)kb * a.ncb + cb0 + c) * 2 + h) * 64 + lane];
+      // generate the block's 8 word pairs (uniform control flow)
+      const unsigned st = starts[kb];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const StepPair r = load_steps(tab + kb * 8 + i);  // one scalar load of both records
+        const bool later = kb > 0 || i > 0;  // not the chains' first order
+        if ((st >> i) & 1u) {  // chain A starts an order
+          qa2 = 1.0;
+          if (later) {  // (x + iy)^(m+1)
+            const double nr = cra * ux - cia * uy, ni = cra * uy + cia * ux;
+            cra = nr;
+            cia = ni;
+            crsa = (float)(nr * sc);
+            cisa = (float)(ni * sc);
           }
-          const float q = (float)rec_step(tab + 4 * st, uz, q1, q2);
-          u = q * crs;
-          v = q * cis;
         }
-        unsigned hw, lw;
-        split_pair(u, v, hw, lw);
-        hiP[(rb + w) * kRingStride + lane] = hw;
-        loP[(rb + w) * kRingStride + lane] = lw;
+        if ((st >> (8 + i)) & 1u) {  // chain B
+          qb2 = 1.0;
+          if (later) {
+            const double nr = crb * ux - cib * uy, ni = crb * uy + cib * ux;
+            crb = nr;
+            cib = ni;
+            crsb = (float)(nr * sc);
+            cisb = (float)(ni * sc);
+          }
+        }
+        const float qa = (float)rec_step(r.a, uz, qa1, qa2);
+        const float qb = (float)rec_step(r.b, uz, qb1, qb2);
+        uint2 hw, lw;  // (chain A word, chain B word)
+        split_pair(qa, crsa, cisa, hw.x, lw.x);
+        split_pair(qb, crsb, cisb, hw.y, lw.y);
+        *(uint2*)&hiP[i * kRingStride + 2 * lane] = hw;
+        *(uint2*)&loP[i * kRingStride + 2 * lane] = lw;
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // A operands of the four 16-point row blocks
+      // A operands of the four 16-point row blocks: lane t takes the words
+      // 4 (t / 16) .. + 3, i.e. the pairs 2 (t / 16) and + 1
       half8 ah[4], al[4];
-      const int r0 = rb + 4 * (lane >> 4);
+      const int p0r = 2 * (lane >> 4);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int col = r * 16 + (lane & 15);
-        uint4 h4, l4;
-        h4.x = hiP[(r0 + 0) * kRingStride + col];
-        h4.y = hiP[(r0 + 1) * kRingStride + col];
-        h4.z = hiP[(r0 + 2) * kRingStride + col];
-        h4.w = hiP[(r0 + 3) * kRingStride + col];
-        l4.x = loP[(r0 + 0) * kRingStride + col];
-        l4.y = loP[(r0 + 1) * kRingStride + col];
-        l4.z = loP[(r0 + 2) * kRingStride + col];
-        l4.w = loP[(r0 + 3) * kRingStride + col];
-        ah[r] = __builtin_bit_cast(half8, h4);
-        al[r] = __builtin_bit_cast(half8, l4);
+        const int col = 2 * (r * 16 + (lane & 15));
+        const uint2 h0 = *(const uint2*)&hiP[p0r * kRingStride + col];
+        const uint2 h1 = *(const uint2*)&hiP[(p0r + 1) * kRingStride + col];
+        const uint2 l0 = *(const uint2*)&loP[p0r * kRingStride + col];
+        const uint2 l1 = *(const uint2*)&loP[(p0r + 1) * kRingStride + col];
+        ah[r] = __builtin_bit_cast(half8, uint4{h0.x, h0.y, h1.x, h1.y});
+        al[r] = __builtin_bit_cast(half8, uint4{l0.x, l0.y, l1.x, l1.y});
       }
+      // the ring is rewritten by the next block only after these reads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // hi hi, hi lo, lo hi: each pass over all 4 x NCB accumulators before
       // the next touches one again (the operands of absent column blocks are
       // zero: no branches between the MFMAs)
@@ -267,7 +309,6 @@ __global__ __launch_bounds__(256, 2) void k_bank_synth(BankArgs a) {
       for (int i = 0; i < 4; ++i) mh[r][i] = 0.0;
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
-      if (c >= nact) continue;
       const int col = (cb0 + c) * 16 + (lane & 15);
       const bool colok = col < a.n_rows;
 #pragma unroll
@@ -278,13 +319,13 @@ __global__ __launch_bounds__(256, 2) void k_bank_synth(BankArgs a) {
         for (int i = 0; i < 4; ++i) {
           const int pt = pt0 + i;
           const int fl = flags[pt];
-          const double h = (fl & 1) ? a.dc_value : (double)(acc[r][c][i] * a.out_scale);
+          // columns past the rows have zero steering operands (h = 0) and
+          // no DC value: they add exact zeros
+          const double h = (fl & 1) ? (colok ? a.dc_value : 0.0) : (double)(acc[r][c][i] * a.out_scale);
           const float v = (float)(gsh[pt] * h);
           vv[i] = v;
-          if (colok) {
-            mh[r][i] += (double)v * (double)v;
-            if (fl & 2) asum += (double)v;
-          }
+          mh[r][i] += (double)v * (double)v;
+          asum += (fl & 2) ? (double)v : 0.0;
         }
         if (colok) {
           float* dst = a.psi + (long long)col * a.V + p0 + pt0;
@@ -500,14 +541,13 @@ int launch_build_bank(os3d_bank* b, void* stream) {
   a.Mh = b->d.Mh;
   a.part = b->d.part;
   a.dc_value = b->dc_value;
-  a.ncb = b->Npad / 16;
+  a.ncb = synth_padded_blocks(b->Npad / 16);
   a.kblocks = b->kblocks;
+  a.mb = b->synth_mb;
   a.out_scale = b->synth_scale;
   const long long nblk = (b->V + kBankPts - 1) / kBankPts;
   void* tok = prof_start(st, PROF_BANK);
-  // 16-column blocks per sweep: at most kMaxNcb, the sweeps evenly filled
-  const int sweeps = (a.ncb + kMaxNcb - 1) / kMaxNcb;
-  switch ((a.ncb + sweeps - 1) / sweeps) {
+  switch (synth_sweep_blocks(b->Npad / 16)) {  // 16-column blocks per sweep
     case 1: launch_k(k_bank_synth<1>, dim3((unsigned)nblk), dim3(256), 0, st, a); break;
     case 2: launch_k(k_bank_synth<2>, dim3((unsigned)nblk), dim3(256), 0, st, a); break;
     case 3: launch_k(k_bank_synth<3>, dim3((unsigned)nblk), dim3(256), 0, st, a); break;

@@ -105,9 +105,9 @@ static BankLayout layout(const int64_t dims[3], int n_unique, int L) {
   b.Mh = o;
   o = align256(o + V * sizeof(double));
   b.S = o;
-  o = align256(o + (size_t)synth_kblocks(L) * (Npad / 16) * 2 * 64 * 16);
+  o = align256(o + (size_t)synth_kblocks(L) * synth_padded_blocks(Npad / 16) * 2 * 64 * 16);
   b.tab = o;
-  o = align256(o + (size_t)4 * (2 * ((L + 2) / 2) + L * nn / 2) * sizeof(double));
+  o = align256(o + (size_t)synth_kblocks(L) * (8 * 4 * sizeof(double) + sizeof(uint32_t)));
   b.part = o;  // band partials of the synthesis workgroups (3 each), then kappa and S
   o = align256(o + (3 * ((V + 255) / 256) + 2) * sizeof(double));
   for (int d = 0; d < 3; ++d) {
@@ -233,19 +233,22 @@ os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_
   const int eS = smax > 0.0 ? 14 - (int)std::floor(std::log2(smax)) : 0;
   b->synth_scale = (float)std::ldexp(1.0, -(13 + eS));
   b->kblocks = synth_kblocks(L);
-  const int ncb = b->Npad / 16;
+  const int ncb = synth_padded_blocks(b->Npad / 16);
   // operand order of v_mfma_f32_16x16x32_f16's B: lane t holds column t % 16
   // and the eight K entries 8 (t / 16) .. + 7, two per word (low half first)
   std::vector<uint32_t> S((size_t)b->kblocks * ncb * 2 * 64 * 4, 0u);
+  const std::vector<int> order = synth_word_order(L);
   for (int kb = 0; kb < b->kblocks; ++kb)
     for (int cb = 0; cb < ncb; ++cb)
       for (int t = 0; t < 64; ++t) {
         const int col = cb * 16 + (t & 15);
         for (int j = 0; j < 8; ++j) {
-          int l, m;
-          bool sn;
+          const int e = kb * 32 + 8 * (t >> 4) + j;  // entry: word e / 2, cos (even) or sin (odd)
+          const int lm = order[e >> 1];
+          const int l = lm / (L + 1), m = lm % (L + 1);
+          const bool sn = (e & 1) == 1;
           float v = 0.f;
-          if (col < b->n_unique && synth_entry(L, kb * 32 + 8 * (t >> 4) + j, l, m, sn)) {
+          if (col < b->n_unique && lm >= 0 && !(m == 0 && sn)) {
             const int idx = l * l + l + (sn ? -m : m);
             v = (float)std::ldexp(Sstd[(size_t)idx * b->n_unique + col], eS);
           }
@@ -261,30 +264,36 @@ os3d_status os3d_build_bank(const int64_t dims[3], const double* orients, int32_
         }
       }
   ShTables t = sh_tables(L);
-  // the recursion steps in the synthesis order (Q = alpha (z Q' - beta Q'')
-  // + gamma, a flag where an order m >= 1 starts): m = 0 in 2 ((L + 2) / 2)
-  // steps (the last one zero when L is even), then l = m..L for m = 1..L
-  const int w0 = (L + 2) / 2;
-  std::vector<double> tab((size_t)4 * (2 * w0 + L * nn / 2), 0.0);
-  auto put_step = [&](int s, int l, int m) {
-    double* r = &tab[(size_t)4 * s];
-    if (l == m) {
-      r[2] = t.qmm[m];
-      if (m > 0) {
-        const long long one = 1;
-        std::memcpy(&r[3], &one, sizeof one);
+  // the recursion steps in the synthesis order, per word pair the records
+  // (c0, c1) of chains A and B, Q = c0 (z Q') - c1 Q'': inside an order
+  // (alpha, alpha beta), where an order starts (0, -Q_m^m) with Q'' set to 1
+  // by the device (zero records past a chain's end); then per K-block a mask
+  // with bit i (chain A) or 8 + i (chain B) set where pair i starts an order
+  // (the chain then also multiplies its (x + iy)^m by x + iy, except at its
+  // first order)
+  const int M = synth_split(L);
+  std::vector<double> tab((size_t)b->kblocks * 8 * 4 + (b->kblocks + 1) / 2, 0.0);
+  std::vector<uint32_t> starts(b->kblocks, 0u);
+  auto put_chain = [&](int chain, int m0, int m1) {
+    int i = 0;
+    for (int m = m0; m <= m1; ++m)
+      for (int l = m; l <= L; ++l, ++i) {
+        double* r = &tab[(size_t)4 * i + 2 * chain];
+        if (l == m) {
+          r[1] = -t.qmm[m];
+          starts[i / 8] |= 1u << (8 * chain + i % 8);
+        } else if (l == m + 1) {
+          r[0] = std::sqrt(2.0 * m + 3.0);
+        } else {
+          r[0] = t.alm[l * nn + m];
+          r[1] = t.alm[l * nn + m] * t.blm[l * nn + m];
+        }
       }
-    } else if (l == m + 1) {
-      r[0] = std::sqrt(2.0 * m + 3.0);
-    } else {
-      r[0] = t.alm[l * nn + m];
-      r[1] = t.blm[l * nn + m];
-    }
   };
-  for (int l = 0; l <= L; ++l) put_step(l, l, 0);
-  int step = 2 * w0;
-  for (int m = 1; m <= L; ++m)
-    for (int l = m; l <= L; ++l) put_step(step++, l, m);
+  put_chain(0, 0, M);
+  put_chain(1, M + 1, L);
+  std::memcpy(&tab[(size_t)b->kblocks * 8 * 4], starts.data(), starts.size() * sizeof(uint32_t));
+  b->synth_mb = M + 1;
   std::vector<float> tw[3];
   for (int d = 0; d < 3; ++d) {
     const int N = (int)dims[d];

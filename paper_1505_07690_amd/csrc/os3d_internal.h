@@ -39,13 +39,25 @@ struct ShTables {
 ShTables sh_tables(int L);
 void real_sh(const ShTables& t, const double n[3], double* Y);  // index l*l + l + m
 
-// Contraction order (K) of the bank synthesis: m = 0 with l = 0..L (padded
-// to an even count), then for m = 1..L and l = m..L the pair (cos, sin).
-// Two consecutive entries share one 32-bit word of fp16 values; 16 words
-// (32 entries) are one K-block of the 16x16x32 fp16 MFMA.
-int synth_words(int L);                                        // (L + 2) / 2 + L (L + 1) / 2
+// Contraction order (K) of the bank synthesis.  The orders m = 0..L are
+// split into two chains of the recursion, A = 0..M and B = M + 1..L, M
+// balancing their lengths (one step per (l, m), l = m..L, orders ascending);
+// word 2i is step i of chain A, word 2i + 1 step i of chain B (zero past a
+// chain's end).  A word holds the entries (cos, sin) of its (l, m) as two
+// fp16 values (the sin entry of m = 0 is zero); 16 words (32 entries) are
+// one K-block of the 16x16x32 fp16 MFMA.
+int synth_split(int L);                                        // M
+int synth_pairs(int L);                                        // steps of the longer chain
+int synth_words(int L);                                        // 2 synth_pairs(L)
 int synth_kblocks(int L);                                      // ceil(words / 16)
-bool synth_entry(int L, int e, int& l, int& m, bool& sin_part);  // false for padding
+// The stored rows go through the synthesis in sweeps of at most
+// kSynthMaxBlocks 16-column blocks, the sweeps evenly filled; the packed
+// steering operands hold synth_padded_blocks (zero past the rows).
+constexpr int kSynthMaxBlocks = 6;
+int synth_sweep_blocks(int ncb);                               // blocks per sweep
+int synth_padded_blocks(int ncb);                              // sweeps x blocks per sweep
+bool synth_entry(int L, int e, int& l, int& m, bool& sin_part);  // false for a zero entry
+std::vector<int> synth_word_order(int L);  // per word of the K-blocks: l (L + 1) + m, or -1
 
 void steering_std(const os3d_wavelet_params& p, const double* orients, int n, const std::vector<double>& a,
                   double* S);  // [(L+1)^2][n], standard order
@@ -67,8 +79,9 @@ struct DevPtrs {
   float* psi;      // [n_unique][V] float32 g h without kappa (the transforms apply kappa)
   float* M;        // [V]
   double* Mh;      // [V] FP64 sum over stored rows of raw psi^2 (build scratch)
-  uint32_t* S;     // steering matrix as fp16 hi / lo MFMA operands: [kblocks][Npad / 16][2][64][4 words]
-  double* tab;     // recursion steps of the synthesis: [steps][alpha, beta, gamma, order-start flag]
+  uint32_t* S;     // steering matrix as fp16 hi / lo MFMA operands: [kblocks][padded blocks][2][64][4 words]
+  double* tab;     // recursion steps of the synthesis: [kblocks * 8][chain A, B][c0, c1],
+                   // then [kblocks] 32-bit order-start masks
   double* part;    // band partials of the synthesis, then kappa and S
   float* tw[3];    // twiddles exp(-2 pi i j / N_d), j < N_d, per axis (z, y, x)
 };
@@ -86,6 +99,7 @@ struct os3d_bank {
   int L;
   int Npad;
   int kblocks;                // K-blocks of the synthesis contraction
+  int synth_mb;               // first order of the synthesis' second recursion chain
   float synth_scale;          // 2^-(13 + e_S): undoes the fp16 operand scaling
   double kappa;
   double dc_value;            // a_0 / sqrt(4 pi): the sphere average of h, used at k = 0

@@ -4,6 +4,7 @@
 // undefined-behaviour sanitizers by tests/test_host_sanitizers.py.  It prints
 // the coefficients for the parameter grid the test compares with the oracle,
 // and checks the plans and layouts itself; any sanitizer report fails the run.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -56,37 +57,56 @@ int main() {
     ++plans;
   }
   // the contraction order of the bank kernel addresses every (l, m, cos / sin)
-  // once, within its K-blocks, and the device's generation order (m = 0 in
-  // pairs of l, then one (cos, sin) word per l) gives the same word indices
+  // once (no sin entry for m = 0) within its K-blocks; the even words run
+  // through the orders 0..M and the odd words through M + 1..L, each in the
+  // recursion's order (l = m..L, orders ascending), and M balances the two
   for (int L : Ls) {
+    const int M = synth_split(L);
     const int ne = 32 * synth_kblocks(L);
     if (ne < 2 * synth_words(L) || ne >= 2 * synth_words(L) + 32) ++bad;
     std::vector<int> seen((size_t)(L + 1) * (L + 1) * 2, 0);
     int used = 0;
+    int last[2][2] = {{-1, -1}, {-1, -1}};  // per chain: previous (m, l)
     for (int e = 0; e < ne; ++e) {
       int l, m;
       bool sn;
       if (!synth_entry(L, e, l, m, sn)) continue;
       if (l < m || l > L || (m == 0 && sn)) ++bad;
+      const int chain = (e >> 1) & 1;
+      if ((chain == 0) != (m <= M)) ++bad;
+      if (!sn) {  // steps of a chain in the recursion's order
+        int* pv = last[chain];
+        const bool next = (m == pv[0] && l == pv[1] + 1) || (m == pv[0] + 1 && l == m && pv[1] == L) ||
+                          (pv[0] < 0 && l == m && m == (chain == 0 ? 0 : M + 1));
+        if (!next) ++bad;
+        pv[0] = m;
+        pv[1] = l;
+      }
       ++seen[(size_t)(l * (L + 1) + m) * 2 + (sn ? 1 : 0)];
       ++used;
     }
     for (int v : seen)
       if (v > 1) ++bad;
     if (used != (L + 1) * (L + 1)) ++bad;
-    int w = 0;
-    for (int l = 0; l <= L; l += 2, ++w) {
-      int l2, m2;
-      bool s2;
-      if (!synth_entry(L, 2 * w, l2, m2, s2) || l2 != l || m2 != 0) ++bad;
+    // the precomputed word order the host packs the operands by
+    const std::vector<int> order = synth_word_order(L);
+    if ((int)order.size() * 2 != ne) ++bad;
+    for (int e = 0; e < ne; ++e) {
+      int l, m;
+      bool sn;
+      const bool ok = synth_entry(L, e, l, m, sn);
+      const int lm = order[e >> 1];
+      const bool ok2 = lm >= 0 && !(lm % (L + 1) == 0 && (e & 1) == 1);
+      if (ok != ok2 || (ok && lm != l * (L + 1) + m)) ++bad;
     }
-    for (int m = 1; m <= L; ++m)
-      for (int l = m; l <= L; ++l, ++w) {
-        int l2, m2;
-        bool s2;
-        if (!synth_entry(L, 2 * w + 1, l2, m2, s2) || l2 != l || m2 != m || !s2) ++bad;
-      }
-    if (w != synth_words(L)) ++bad;
+    // balance: no other split has a shorter longer chain
+    auto words = [&](int m0, int m1) {
+      int n = 0;
+      for (int m = m0; m <= m1; ++m) n += L + 1 - m;
+      return n;
+    };
+    for (int M2 = 0; M2 <= L; ++M2)
+      if (std::max(words(0, M2), words(M2 + 1, L)) < synth_pairs(L)) ++bad;
   }
   std::printf("plans %d bad %d\n", plans, bad);
   return bad ? 1 : 0;
