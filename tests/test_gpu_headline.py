@@ -10,7 +10,7 @@ The oracle runs in this process, streamed so that it never holds the full
   orientations);
 * M (Eq. 9) at about 2e5 sampled frequencies, a quarter of them within 0.1
   rho_N of the Nyquist radius;
-* eight whole bank rows (both 48-column sweeps of the contraction), each
+* eight whole bank rows (every 16-column block of the contraction), each
   orientation's partner read through the reflected row;
 * the scores of those eight stored orientations and of their antipodal
   partners, complex64 and 16-bit storage, with the 16-bit scales checked
@@ -90,7 +90,7 @@ def _scores(hl):
     return hl["Us"]
 
 
-# stored rows on both 48-column sweeps of the contraction (rows 0-47, 48-80)
+# stored rows in every 16-column block of the contraction (rows 16 j .. 16 j + 15)
 ROWS = (0, 13, 29, 47, 48, 61, 72, 80)
 
 
