@@ -48,6 +48,8 @@ struct PassArgs {
   void* Uout;
   float out_scale;
   float* partial;        // [nb][tiles] sums of |value| (scale bound), or null
+  const float* tsc;      // 256^3 fp16 intermediates: scales of the writing workgroups [nb][1024]
+  float* tsc_out;        // where the writing pass puts them
   int accumulate;        // SM_ACCUM: 1 adds to X, 0 overwrites
   int phi_kind;          // SM_PHI: 0 identity, 1 |U|^phi_p sgn(U)
   float phi_p;

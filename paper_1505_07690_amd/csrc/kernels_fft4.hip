@@ -66,6 +66,51 @@ __device__ __forceinline__ int reader_tile(int b) {
   return (((i >> 2) << 3) + xcd) * 4 + (i & 3);
 }
 
+// 16-bit intermediates.  With bf16 score storage the intermediate T of a
+// pair is stored as fp16 pairs (4 instead of 8 bytes a value, the same
+// element order, packed into the first half of the pair's slot), each
+// writing workgroup's values with its own power-of-two scale s: the
+// workgroup takes the largest |component| m of its 16384 values, s =
+// 2^(e - 15) with m <= 2^e, so every value is finite and those down to
+// 2^-29 m are normal (about 1.4e-4 relative RMS, well below bf16 storage's
+// 1.7e-3; the reconstruction's division by max(M, eps) amplifies errors
+// spread into the spectrum's corners, which rules out bf16 intermediates
+// and keeps fp16 scores on complex64 intermediates).  The scales, one
+// float per writing workgroup and pair, follow the pairs' values in the
+// intermediate buffer.  A reading workgroup gathers its 16 values per
+// thread from 16 writers and looks up each one's scale.
+__device__ __forceinline__ float t16_scale(float m) {
+  if (!(m > 0.f)) return 1.f;
+  int e;
+  frexpf(m, &e);  // m <= 2^e
+  return ldexpf(1.f, e - 15);
+}
+
+__device__ __forceinline__ unsigned int pack_f16(float2 v, float inv) {
+  return (unsigned int)__half_as_ushort(__float2half_rn(v.x * inv)) |
+         ((unsigned int)__half_as_ushort(__float2half_rn(v.y * inv)) << 16);
+}
+
+__device__ __forceinline__ float2 unpack_f16(unsigned int q, float s) {
+  return make_float2(__half2float(__ushort_as_half((unsigned short)(q & 0xffffu))) * s,
+                     __half2float(__ushort_as_half((unsigned short)(q >> 16))) * s);
+}
+
+// The scale of this workgroup's 16 values per thread (all threads get it).
+// red: 16 floats of LDS; the caller synchronises before red is reused.
+__device__ __forceinline__ float tile_scale(const float2 (&u)[16], float* red) {
+  float m = 0.f;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) m = fmaxf(m, fmaxf(fabsf(u[r].x), fabsf(u[r].y)));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  float b = red[0];
+#pragma unroll
+  for (int w = 1; w < 16; ++w) b = fmaxf(b, red[w]);
+  return t16_scale(b);
+}
+
 // exp(sg 2 pi i m / 256) for the direction sg of the kernel (the table holds sg = -1)
 template <int SG>
 __device__ __forceinline__ void load_twiddles(const PassArgs& a, float2* twl) {
@@ -88,11 +133,12 @@ constexpr float kInv = 1.f, kFwd = -1.f;
 // prefetched while the current pair is transformed), z DFT (two stages),
 // step A over n2 and the twiddle w^(n1 k2).  Consecutive workgroups take
 // consecutive kxb, so the 128-byte runs they write into T are adjacent.
-template <int LM>
+template <int LM, bool T16 = false>
 __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
   __shared__ float red[16];
+  __shared__ float red_t[16];
   const int t = threadIdx.x;
   const int kxb = blockIdx.x & 63, n1 = blockIdx.x >> 6, tile = kxb * 16 + n1;
   const int g = t & 3, s = (t >> 2) & 15, n2 = t >> 6;
@@ -154,16 +200,27 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
     dft16(u, kInv);
 #pragma unroll
     for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[n1 * k2]);
-    float2* T = a.dst_c + (long long)j * a.dst_stride;
     const long long o = (long long)((zb >> 2) * 16 + n1) * 4096 + kxb * 64 + (zb & 3) * 16 + zz * 4 + g;
+    if constexpr (!T16) {
+      float2* T = a.dst_c + (long long)j * a.dst_stride;
 #pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = u[k2];
+      for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = u[k2];
+    } else {
+      // its own LDS words: the next pair's scale-bound sum reuses red before
+      // the next barrier
+      const float sT = tile_scale(u, red_t);
+      unsigned int* T = (unsigned int*)a.dst_c + (long long)j * a.dst_stride;
+      const float inv = 1.f / sT;  // a power of two: exact
+#pragma unroll
+      for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = pack_f16(u[k2], inv);
+      if (t == 0) a.tsc_out[(long long)j * gridDim.x + blockIdx.x] = sT;
+    }
   }
 }
 
 // Natural side of the inverse direction: T tile (k2, zb) -> rows of four z
 // planes.  Step C over n1, then the x DFT (two stages), then the fused store.
-template <int SM, int DT>
+template <int SM, int DT, bool T16 = false>
 __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
@@ -171,11 +228,26 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
   const int tile = reader_tile(blockIdx.x), k2 = tile >> 6, zb = tile & 63;
   const int j = blockIdx.y;
   load_twiddles<1>(a, twl);
-  const float2* T = a.src_c + (long long)j * a.src_stride + (long long)(k2 * 16 + (zb >> 2)) * 16 * 4096 +
-                    (t >> 4) * 64 + (zb & 3) * 16 + (t & 15);
+  const long long to = (long long)j * a.src_stride + (long long)(k2 * 16 + (zb >> 2)) * 16 * 4096 + (t >> 4) * 64 +
+                       (zb & 3) * 16 + (t & 15);
   float2 v[16];
+  if constexpr (!T16) {
+    const float2* T = a.src_c + to;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) v[q] = T[q * 4096];
+    for (int q = 0; q < 16; ++q) v[q] = T[q * 4096];
+  } else {
+    // value q was written by the frequency-side workgroup (kxb = t / 16, n1 = q)
+    const unsigned int* T = (const unsigned int*)a.src_c + to;
+    const float* sc = a.tsc + (long long)j * 1024 + (t >> 4);
+    unsigned int w[16];
+    float sT[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) w[q] = T[q * 4096];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sT[q] = sc[q * 64];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = unpack_f16(w[q], sT[q]);
+  }
   dft16(v, kInv);  // over n1 -> k1
   {
     const int g = (t >> 2) & 3, kx = (t >> 4) * 4 + (t & 3);
@@ -206,10 +278,11 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
 // planes -> T.  x DFT (two stages), then step A over n2 with w^(n1 k2).
 // Consecutive workgroups take consecutive n1: sixteen of them read all 256
 // rows of the same four planes.
-template <int LM, int DT>
+template <int LM, int DT, bool T16 = false>
 __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
+  __shared__ float red[16];
   const int t = threadIdx.x;
   const int zb = blockIdx.x >> 4, n1 = blockIdx.x & 15;
   const int j = blockIdx.y;
@@ -239,10 +312,19 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
   dft16(u, kFwd);
 #pragma unroll
   for (int k2 = 1; k2 < 16; ++k2) u[k2] = cmul(u[k2], twl[n1 * k2]);
-  float2* T = a.dst_c + (long long)j * a.dst_stride;
   const long long o = (long long)((kxb >> 2) * 16 + n1) * 4096 + zb * 64 + (kxb & 3) * 16 + zz * 4 + kxx;
+  if constexpr (!T16) {
+    float2* T = a.dst_c + (long long)j * a.dst_stride;
 #pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = u[k2];
+    for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = u[k2];
+  } else {
+    const float sT = tile_scale(u, red);
+    unsigned int* T = (unsigned int*)a.dst_c + (long long)j * a.dst_stride;
+    const float inv = 1.f / sT;  // a power of two: exact
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = pack_f16(u[k2], inv);
+    if (t == 0) a.tsc_out[(long long)j * gridDim.x + blockIdx.x] = sT;
+  }
 }
 
 // Natural side of both directions, for processing via scores: inverse T
@@ -317,7 +399,7 @@ __global__ __launch_bounds__(k4Threads) void k4_nat_phi(PassArgs a) {
 // Frequency side of the forward direction: T tile (k2, kxb) -> Phi tile
 // (kxb, n1 = k2).  Step C over n1, then the z DFT (two stages), then the
 // fused store (F) or the weighted orientation sum over the pair batch (X).
-template <int SM>
+template <int SM, bool T16 = false>
 __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
@@ -331,11 +413,26 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = make_float2(0.f, 0.f);
   for (int j = jb; j < je; ++j) {
-    const float2* T = a.src_c + (long long)j * a.src_stride + (long long)(k2 * 16 + (kxb >> 2)) * 16 * 4096 +
-                      (t >> 4) * 64 + (kxb & 3) * 16 + (t & 15);
+    const long long to = (long long)j * a.src_stride + (long long)(k2 * 16 + (kxb >> 2)) * 16 * 4096 +
+                         (t >> 4) * 64 + (kxb & 3) * 16 + (t & 15);
     float2 v[16];
+    if constexpr (!T16) {
+      const float2* T = a.src_c + to;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = ldnt(T + q * 4096);
+      for (int q = 0; q < 16; ++q) v[q] = ldnt(T + q * 4096);
+    } else {
+      // value q was written by the natural-side workgroup (zb = t / 16, n1 = q)
+      const unsigned int* T = (const unsigned int*)a.src_c + to;
+      const float* sc = a.tsc + (long long)j * 1024 + (t >> 4) * 16;
+      unsigned int w[16];
+      float sT[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) w[q] = ldnt(T + q * 4096);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) sT[q] = sc[q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) v[q] = unpack_f16(w[q], sT[q]);
+    }
     dft16(v, kFwd);  // over n1 -> k1
     {
       const int g = t & 3, z = t >> 2;
@@ -397,10 +494,13 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
   hipStream_t st = (hipStream_t)stream;
   const long long V = b->V;
   float2* F = (float2*)ws;
-  float2* T = F + V;
+  float2* T = F + V;  // nbmax intermediates
   float* partial = (float*)(T + (long long)nbmax * V);
+  // bf16 scores: fp16 intermediates in the first half of T, their scales after them
+  float* tsc = (float*)((unsigned int*)T + (long long)nbmax * V);
   const size_t ubytes = (dtype == OS3D_C64) ? 8 : 4;
   const bool quant = dtype != OS3D_C64;
+  const bool t16 = dtype == OS3D_BF16X2;
   int rc;
   for (int bi = 0; bi < batch; ++bi) {
     {  // F = DFT(f) into the frequency tiles
@@ -413,6 +513,7 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
       c.dst_c = F;
       OS3D_LAUNCH4((k4_fwd_phi<SM_C>), kProfDftLast, 0.0, c, 1);
     }
+
     void* Ub = (char*)U + (size_t)bi * b->n_orients * V * ubytes;
     float* sc = scales ? scales + (long long)bi * b->n_orients : nullptr;
     for (int r0 = 0; r0 < b->n_unique; r0 += nbmax) {
@@ -433,9 +534,14 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
       z.dst_c = T;
       z.dst_stride = V;
       z.partial = quant ? partial : nullptr;
+      z.tsc = tsc;
+      z.tsc_out = tsc;
       {
         void* tok = prof_start(st, kProfFwdFirst);
-        launch_k((k4_inv_phi<LM_MULBANK>), dim3(1024), dim3(k4Threads), 0, st, z);
+        if (t16)
+          launch_k((k4_inv_phi<LM_MULBANK, true>), dim3(1024), dim3(k4Threads), 0, st, z);
+        else
+          launch_k((k4_inv_phi<LM_MULBANK>), dim3(1024), dim3(k4Threads), 0, st, z);
         prof_stop(tok, st, kProfFwdFirst, 0.0, 0.0);
         if ((rc = check("k4_inv_phi"))) return rc;
       }
@@ -458,7 +564,7 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
         if (dtype == OS3D_C64)
           launch_k((k4_inv_nat<SM_UOUT, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else if (dtype == OS3D_BF16X2)
-          launch_k((k4_inv_nat<SM_UOUT, OS3D_BF16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_inv_nat<SM_UOUT, OS3D_BF16X2, true>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else
           launch_k((k4_inv_nat<SM_UOUT, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfFwdLast, nor * (double)V * (double)ubytes, 0.0);
@@ -475,6 +581,8 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
   const long long V = b->V;
   float2* X = (float2*)ws;
   float2* T = X + V;
+  // bf16 scores: fp16 intermediates in the first half of T, their scales after them
+  float* tsc = (float*)((unsigned int*)T + (long long)nbmax * V);
   const size_t ubytes = (dtype == OS3D_C64) ? 8 : 4;
   int rc;
   for (int bi = 0; bi < batch; ++bi) {
@@ -497,12 +605,14 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
       x.scales = (dtype == OS3D_C64) ? nullptr : sc;
       x.dst_c = T;
       x.dst_stride = V;
+      x.tsc = tsc;
+      x.tsc_out = tsc;
       {
         void* tok = prof_start(st, kProfRecFirst);
         if (dtype == OS3D_C64)
           launch_k((k4_fwd_nat<LM_UIN, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else if (dtype == OS3D_BF16X2)
-          launch_k((k4_fwd_nat<LM_UIN, OS3D_BF16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_fwd_nat<LM_UIN, OS3D_BF16X2, true>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else
           launch_k((k4_fwd_nat<LM_UIN, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfRecFirst, nor * (double)V * (double)ubytes, 0.0);
@@ -515,7 +625,10 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
       z.kappa = (float)b->kappa;
       z.dst_c = X;
       z.accumulate = (r0 > 0) ? 1 : 0;
-      OS3D_LAUNCH4((k4_fwd_phi<SM_ACCUM>), kProfRecLast, 0.0, z, 1);
+      if (dtype == OS3D_BF16X2)
+        OS3D_LAUNCH4((k4_fwd_phi<SM_ACCUM, true>), kProfRecLast, 0.0, z, 1);
+      else
+        OS3D_LAUNCH4((k4_fwd_phi<SM_ACCUM>), kProfRecLast, 0.0, z, 1);
     }
     PassArgs z = base_args(b, 1.f);
     z.src_c = X;

@@ -205,3 +205,25 @@ def test_largest_volume_gram_and_norm_identities(torch):
         num += torch.sum((adj[z0:z0 + 128].double() - ref) ** 2).item()
         den += torch.sum(ref ** 2).item()
     assert np.sqrt(num / den) < 1e-5
+
+
+def test_bf16_intermediates_take_their_scale_from_the_data(torch):
+    """With bf16 score storage the 256^3 path keeps its intermediates as fp16
+    pairs, each writing workgroup's values under its own power-of-two scale.
+    Power-of-two factors commute exactly with every step, so scaling f by
+    2^30 (intermediates near 1e14, far past fp16's 65504) must give the same
+    stored scores with scales times 2^30, and scaling the scales by 2^30 must
+    scale the reconstruction by exactly 2^30."""
+    from paper_1505_07690_amd import os3d
+    shape = (256, 256, 256)
+    n = inputs.icosahedral_orientations(0)
+    gb = os3d.Bank(shape, n, _params(4, len(n)))
+    f = torch.from_numpy(inputs.tubes(shape, 12, (1.0, 3.0), 0.2, 0, 33)).cuda()
+    Uq, sc = os3d.forward(f, gb, dtype="bf16")
+    Uq2, sc2 = os3d.forward(f * 2.0 ** 30, gb, dtype="bf16")
+    assert torch.equal(Uq2, Uq)
+    assert torch.equal(sc2, sc * 2.0 ** 30)
+    r = os3d.reconstruct(Uq, gb, scales=sc, dtype="bf16")
+    r2 = os3d.reconstruct(Uq, gb, scales=sc * 2.0 ** 30, dtype="bf16")
+    assert torch.isfinite(r2).all()
+    assert torch.equal(r2, r * 2.0 ** 30)
