@@ -227,3 +227,14 @@ def test_bf16_intermediates_take_their_scale_from_the_data(torch):
     r2 = os3d.reconstruct(Uq, gb, scales=sc * 2.0 ** 30, dtype="bf16")
     assert torch.isfinite(r2).all()
     assert torch.equal(r2, r * 2.0 ** 30)
+    # a batch of two volumes: each one's scores, scales and reconstruction
+    # equal the single-volume calls (the intermediates' scales are rewritten
+    # per volume)
+    fb = torch.stack([f, f * 2.0 ** -12])
+    Ub, scb = os3d.forward(fb, gb, dtype="bf16")
+    assert torch.equal(Ub[0], Uq) and torch.equal(scb[0], sc)
+    U1, sc1 = os3d.forward(f * 2.0 ** -12, gb, dtype="bf16")
+    assert torch.equal(Ub[1], U1) and torch.equal(scb[1], sc1)
+    rb = os3d.reconstruct(Ub, gb, scales=scb, dtype="bf16")
+    assert torch.equal(rb[0], r)
+    assert torch.equal(rb[1], os3d.reconstruct(U1, gb, scales=sc1, dtype="bf16"))
