@@ -107,7 +107,8 @@ static BankLayout layout(const int64_t dims[3], int n_unique, int L) {
   b.S = o;
   o = align256(o + (size_t)synth_kblocks(L) * synth_padded_blocks(Npad / 16) * 2 * 64 * 16);
   b.tab = o;
-  o = align256(o + (size_t)synth_kblocks(L) * (8 * 4 * sizeof(double) + sizeof(uint32_t)));
+  // the synthesis' recursion records, then its order-start masks (packed into doubles)
+  o = align256(o + ((size_t)synth_kblocks(L) * 8 * 4 + (synth_kblocks(L) + 1) / 2) * sizeof(double));
   b.part = o;  // band partials of the synthesis workgroups (3 each), then kappa and S
   o = align256(o + (3 * ((V + 255) / 256) + 2) * sizeof(double));
   for (int d = 0; d < 3; ++d) {
