@@ -375,8 +375,12 @@ def main():
             print("[bench] precision of every storage form against the FP64 oracle", file=sys.stderr, flush=True)
             out["precision_vs_fp64_oracle"] = precision_vs_oracle(sample, keep_gpu, vol, shape)
     if extras:
-        del keep_gpu
-        del U
+        # the remaining forms start from a clean device: the headline's
+        # buffers released and the allocator's cache handed back
+        del keep_gpu, U, rec, fb, f, bank, ws
+        scales = None
+        import gc
+        gc.collect()
         torch.cuda.empty_cache()
         print("[bench] form: differentiation (forward + adjoint of 8 x 128^3)", file=sys.stderr, flush=True)
         forms["differentiation"] = grad_form(dev, args.warmup, args.steps)
@@ -631,8 +635,11 @@ def short_serving(dev, n_requests, rate, cold, budget_gb=160.0, slots=4, max_bat
     st = srv.stats()
     out = {k: st.get(k) for k in ("jobs", "ok", "p50_ms", "p99_ms", "mean_wait_ms", "vo_per_s", "mean_batch",
                                   "bank_hit_rate", "bank_builds", "bank_build_ms_max", "peak_bytes")}
-    out.update(requests=n_requests, rate_per_s=rate, warm_bank_cache=not cold, slots=slots)
+    out.update(requests=n_requests, rate_per_s=rate, warm_bank_cache=not cold, slots=slots,
+               budget_bytes=srv.budget)
     del srv, pool
+    import gc
+    gc.collect()
     torch.cuda.empty_cache()
     return out
 

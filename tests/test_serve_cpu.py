@@ -233,7 +233,10 @@ def test_lru_bank_eviction_and_hit_rate():
         for i, L in enumerate([8, 16, 8, 24, 8, 16]):
             s.submit(vol((8, 8, 8), i), 42, L).result(timeout=5)
         st = s.stats()
-    assert ex.freed == [((8, 8, 8), 42, 16), ((8, 8, 8), 42, 24)]
+        evicted = list(ex.freed)
+    assert evicted == [((8, 8, 8), 42, 16), ((8, 8, 8), 42, 24)]
+    # closing the server released the two banks still cached
+    assert sorted(ex.freed[2:]) == [((8, 8, 8), 42, 8), ((8, 8, 8), 42, 16)]
     assert (st["bank_hits"], st["bank_misses"], st["bank_evictions"]) == (2, 4, 2)
     assert st["peak_bytes"] <= job + 2 * bank + 100
 
@@ -299,7 +302,7 @@ def test_waits_for_running_jobs_instead_of_evicting():
         a.result(timeout=5)
         b.result(timeout=5)
         st = s.stats()
-    assert st["bank_evictions"] == 0 and ex.freed == []
+        assert st["bank_evictions"] == 0 and ex.freed == []
     assert st["ok"] == 3 and st["errors"] == {}
 
 
@@ -364,3 +367,101 @@ def test_a_failed_build_left_in_the_cache_is_evictable():
         st = s.stats()
     assert st["bank_evictions"] >= 1
     assert None not in ex.freed and bad not in ex.freed
+
+
+def test_budget_is_capped_at_the_free_device_memory():
+    """A budget beyond what the device has free would make the allocator
+    release and re-reserve memory mid-stream: the server takes 90 % of the
+    free bytes the executor reports, and keeps the requested value."""
+
+    class Small(FakeExecutor):
+        def device_bytes_available(self):
+            return 10 << 30
+
+    with Server(64 << 30, n_slots=1, executor=Small(1)) as s:
+        assert s.budget == int(0.9 * (10 << 30))
+        assert s.budget_requested == 64 << 30
+    with Server(4 << 30, n_slots=1, executor=Small(1)) as s:
+        assert s.budget == 4 << 30
+    with Server(64 << 30, n_slots=1, executor=FakeExecutor(1)) as s:  # no report: no cap
+        assert s.budget == 64 << 30
+
+
+def test_close_releases_the_cached_banks():
+    """A closed server holds no device memory: every cached bank is freed
+    once the submitted work has finished (a later server in the same
+    process then starts from the memory the first one used)."""
+    ex = FakeExecutor(2)
+    s = Server(1 << 30, n_slots=2, executor=ex)
+    futs = [s.submit(vol((8, 8, 8), i), 12, 8) for i in range(3)] + [s.submit(vol((8, 8, 12), 9), 42, 8)]
+    s.close()
+    assert all(f.done() and f.exception() is None for f in futs)
+    assert sorted(ex.freed) == sorted(ex.built)
+    assert len(ex.built) == 2
+    assert s._used == 0 and not s._banks
+
+
+class ScratchExecutor(FakeExecutor):
+    """A fake executor whose slots keep scratch (half of a launch's
+    footprint) from one launch to the next, as the GPU executor does."""
+
+    def __init__(self, n_slots, **kw):
+        super().__init__(n_slots, **kw)
+        self.slot_bytes = [0] * n_slots
+        self.released = []
+
+    def scratch_bytes(self, key, bank, B, op, dtype):
+        return self.job_bytes(key, bank, B, op, dtype) // 2
+
+    def release_scratch(self, slot):
+        self.released.append(slot)
+        self.slot_bytes[slot] = 0
+
+    def launch(self, slot, bank, jobs):
+        need = self.scratch_bytes(jobs[0].key, bank, len(jobs), jobs[0].op, jobs[0].dtype)
+        self.slot_bytes[slot] = max(self.slot_bytes[slot], need)
+        return super().launch(slot, bank, jobs)
+
+
+def test_slot_scratch_is_reused_and_counted():
+    """A slot's scratch stays counted against the budget between launches,
+    a second job of the same size reuses it (no growth), the accounting
+    matches what the executor holds, and closing the server gives it back."""
+    ex = ScratchExecutor(1, run_s=0.001)
+    key = ((8, 8, 8), 42, 8)
+    bank = ex.bank_bytes(key)
+    job = ex.job_bytes(key, FakeBank(key), 1, "reconstruct", "c64")
+    s = Server(1 << 30, n_slots=1, executor=ex)
+    for i in range(3):
+        s.submit(vol((8, 8, 8), i), 42, 8).result(timeout=5)
+    time.sleep(0.01)
+    assert s._scratch_acc == [job // 2] == ex.slot_bytes
+    assert s._used == bank + job // 2
+    assert s.peak_bytes == bank + job
+    s.close()
+    assert s._used == 0 and ex.released == [0]
+
+
+def test_idle_scratch_is_released_before_a_bank_is_dropped():
+    """Two slots hold the scratch of two finished jobs; a larger job of
+    another key needs room: the idle slot's scratch goes back first and the
+    cached bank of the first key stays."""
+    ex = ScratchExecutor(2, run_s=0.05)
+    ka, kb = ((8, 8, 8), 42, 8), ((8, 8, 16), 42, 8)
+    bank_a, bank_b = ex.bank_bytes(ka), ex.bank_bytes(kb)
+    job_a = ex.job_bytes(ka, FakeBank(ka), 1, "reconstruct", "c64")
+    job_b = ex.job_bytes(kb, FakeBank(kb), 1, "reconstruct", "c64")
+    # room for both banks, one slot's scratch of `a` grown to `b`'s and b's
+    # transient half, but not for the second slot's scratch of `a` on top
+    budget = bank_a + bank_b + job_b + job_a // 2 - 1
+    with Server(budget, n_slots=2, max_batch=1, executor=ex) as s:
+        f1, f2 = s.submit(vol((8, 8, 8), 0), 42, 8), s.submit(vol((8, 8, 8), 1), 42, 8)
+        f1.result(timeout=5)
+        f2.result(timeout=5)
+        time.sleep(0.02)
+        assert sorted(s._scratch_acc) == [job_a // 2, job_a // 2]
+        s.submit(vol((8, 8, 16), 2), 42, 8).result(timeout=5)
+        st = s.stats()
+        assert ex.freed == [] and st["bank_evictions"] == 0
+        assert len(ex.released) == 1
+        assert st["peak_bytes"] <= budget
