@@ -619,9 +619,10 @@ def short_serving(dev, n_requests, rate, cold, budget_gb=160.0, slots=4, max_bat
             for i, sh in enumerate(inputs.SERVING_SHAPES)}
     torch.cuda.synchronize()
     srv = serve.Server(int(budget_gb * (1 << 30)), n_slots=slots, max_batch=max_batch)
-    if not cold:
+    if not cold:  # every key's bank, and every slot's scratch sized for the largest job
         for key in sorted({(sh, n, L) for (_, sh, n, L, _) in reqs}):
             srv.submit(pool[key[0]][0], key[1], key[2]).result()
+        srv.reserve_scratch()
         srv.records.clear()
         srv.bank_hits = srv.bank_misses = 0
         srv.bank_build_s.clear()
@@ -700,9 +701,10 @@ def serve_main(args, dev):
 
     def run_server(times):
         srv = serve.Server(budget, n_slots=args.slots, max_batch=args.max_batch, executor=ex)
-        if not args.cold:  # banks of every key, built before the stream
+        if not args.cold:  # banks of every key and the slots' scratch, before the stream
             for key in sorted({(sh, n, L) for (_, sh, n, L, _) in reqs}):
                 srv.submit(pool[key[0]][0], key[1], key[2]).result()
+            srv.reserve_scratch()
             srv.records.clear()
             srv.bank_hits = srv.bank_misses = 0
         keep = {}

@@ -180,6 +180,7 @@ class Server:
         self._builders = set()
         self._scratch = hasattr(self.ex, "scratch_bytes")
         self._scratch_acc = [0] * self.n_slots  # bytes of each slot's scratch, counted in _used
+        self._controls = collections.deque()     # work for the scheduler thread once every slot is idle
         self._thread = threading.Thread(target=self._loop, name="os3d-serve", daemon=True)
         self._thread.start()
 
@@ -232,6 +233,47 @@ class Server:
         if self._error is not None:
             raise RuntimeError("scheduler failed") from self._error
 
+    def reserve_scratch(self, keys=None, batch=1, op="reconstruct", dtype="c64", timeout=60.0):
+        """Size every slot's scratch for the largest job of `keys` (batches
+        of `batch` jobs) among the cached banks (all of them by default), as
+        far as the budget allows, so that the first launches of a burst do
+        not grow it on the scheduler thread.  Runs on the scheduler thread
+        once every slot is idle (admission pauses meanwhile).  Returns the
+        scratch bytes per slot asked for (0 for executors without scratch)."""
+        if not self._scratch:
+            return 0
+        done, box = threading.Event(), {}
+
+        def run():
+            try:
+                ks = list(self._banks) if keys is None else [(tuple(k[0]), int(k[1]), int(k[2])) for k in keys]
+                need = 0
+                for k in ks:
+                    e = self._banks.get(k)
+                    if e is not None and e.bank is not None:
+                        need = max(need, self.ex.scratch_bytes(k, e.bank, batch, op, dtype))
+                for slot in range(self.n_slots):
+                    grow = need - self._scratch_acc[slot]
+                    if grow > 0 and self.budget - self._used >= grow:
+                        self.ex.grow_scratch(slot, need)
+                        self._account(grow)
+                        self._scratch_acc[slot] = need
+                box["bytes"] = need
+            except Exception as e:  # reported to the caller
+                box["error"] = e
+            done.set()
+
+        with self._cv:
+            if self._closing:
+                raise RuntimeError("server is closed")
+            self._controls.append(run)
+            self._cv.notify()
+        if not done.wait(timeout):
+            raise TimeoutError("reserve_scratch: the slots did not become idle")
+        if "error" in box:
+            raise box["error"]
+        return box["bytes"]
+
     def __enter__(self):
         return self
 
@@ -279,7 +321,13 @@ class Server:
                         return
                 progress = self._reap()
                 progress |= self._expire()
-                progress |= self._admit()
+                if self._controls:  # admission waits until every slot is idle
+                    if not self._inflight and len(self._free_slots) == self.n_slots:
+                        while self._controls:
+                            self._controls.popleft()()
+                        progress = True
+                else:
+                    progress |= self._admit()
                 if not progress:
                     with self._cv:
                         if not self._incoming:
@@ -675,6 +723,9 @@ class GpuExecutor:
 
     def release_scratch(self, slot):
         self._slot_buf[slot] = None
+
+    def grow_scratch(self, slot, nbytes):
+        self._scratch(slot, nbytes)
 
     def _scratch(self, slot, nbytes):
         buf = self._slot_buf[slot]

@@ -417,6 +417,9 @@ class ScratchExecutor(FakeExecutor):
         self.released.append(slot)
         self.slot_bytes[slot] = 0
 
+    def grow_scratch(self, slot, nbytes):
+        self.slot_bytes[slot] = max(self.slot_bytes[slot], nbytes)
+
     def launch(self, slot, bank, jobs):
         need = self.scratch_bytes(jobs[0].key, bank, len(jobs), jobs[0].op, jobs[0].dtype)
         self.slot_bytes[slot] = max(self.slot_bytes[slot], need)
@@ -465,3 +468,23 @@ def test_idle_scratch_is_released_before_a_bank_is_dropped():
         assert ex.freed == [] and st["bank_evictions"] == 0
         assert len(ex.released) == 1
         assert st["peak_bytes"] <= budget
+
+
+def test_reserve_scratch_sizes_every_slot_before_a_burst():
+    """reserve_scratch sizes every slot for the largest cached key, counted
+    against the budget, so that a burst's first launches need no growth."""
+    ex = ScratchExecutor(3, run_s=0.002)
+    ka, kb = ((8, 8, 8), 42, 8), ((8, 8, 16), 162, 8)
+    with Server(1 << 30, n_slots=3, max_batch=1, executor=ex) as s:
+        s.submit(vol((8, 8, 8), 0), 42, 8).result(timeout=5)
+        s.submit(vol((8, 8, 16), 1), 162, 8).result(timeout=5)
+        want = ex.job_bytes(kb, FakeBank(kb), 1, "reconstruct", "c64") // 2
+        assert s.reserve_scratch() == want
+        assert ex.slot_bytes == [want] * 3 and s._scratch_acc == [want] * 3
+        assert s._used == ex.bank_bytes(ka) + ex.bank_bytes(kb) + 3 * want
+        grown = list(ex.slot_bytes)
+        futs = [s.submit(vol((8, 8, 16), 2 + i), 162, 8) for i in range(6)]
+        for f in futs:
+            f.result(timeout=5)
+        assert ex.slot_bytes == grown and s._scratch_acc == [want] * 3
+    assert s._used == 0
