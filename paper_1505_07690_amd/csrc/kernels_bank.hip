@@ -157,7 +157,6 @@ __global__ __launch_bounds__(256, 2) void k_bank_synth(BankArgs a) {
   const long long pw = p0 + wave * 64;  // the wave's first point
   const long long p = p0 + tid;
   const bool valid = p < a.V;
-  const int L = a.L;
   const ctab_t tab = (ctab_t)a.tab;
   const cmask_t starts = (cmask_t)(tab + a.kblocks * 8);  // after the records
   unsigned* hiP = ring[wave][0];

@@ -95,7 +95,6 @@ struct BankLayout {
 static BankLayout layout(const int64_t dims[3], int n_unique, int L) {
   BankLayout b;
   const size_t V = (size_t)dims[0] * dims[1] * dims[2];
-  const int nn = L + 1;
   const int Npad = (n_unique + 15) / 16 * 16;
   size_t o = 0;
   b.psi = o;
