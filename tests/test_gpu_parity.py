@@ -108,6 +108,16 @@ CASES = {
                               inputs.tubes((96, 80, 64), 12, (1.0, 3.0), 0.2, 0, 27)),
     "serve160x128x128": lambda: ((160, 128, 128), inputs.icosahedral_orientations(0), _oracle_params(16, 12),
                                  inputs.tubes((160, 128, 128), 12, (1.0, 3.0), 0.2, 0, 28)),
+    # the ends of the synthesis' K order: L = 1 and L = 3 (a few words, the
+    # chains one or two orders long) and L = 62, the largest order the
+    # synthesis takes (|Y_lm| 2^13 up to 25.8k of fp16's 65504, the recursion
+    # to m = 62)
+    "L1": lambda: ((8, 6, 10), inputs.icosahedral_orientations(0), _oracle_params(1, 12),
+                   inputs.tubes((8, 6, 10), 2, 1.2, 0.1, 0, 34)),
+    "L3": lambda: ((10, 8, 6), inputs.icosahedral_orientations(1), _oracle_params(3, 42),
+                   inputs.tubes((10, 8, 6), 2, 1.2, 0.1, 0, 35)),
+    "L62": lambda: ((6, 8, 10), inputs.icosahedral_orientations(0), _oracle_params(62, 12),
+                    inputs.tubes((6, 8, 10), 2, 1.2, 0.1, 0, 36)),
     # small N with radix-2 only and a long axis
     "long4x6x64": lambda: ((4, 6, 64), inputs.icosahedral_orientations(0), _oracle_params(4, 12),
                            inputs.tubes((4, 6, 64), 2, 1.0, 0.1, 0, 8)),
