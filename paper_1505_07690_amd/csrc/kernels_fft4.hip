@@ -44,14 +44,16 @@ constexpr int k4Sub = 16 * k4LS + 4;  // one sub-problem: 16 lines of 256; the e
 
 __device__ __forceinline__ int pad4(int n) { return n + (n >> 4); }
 
+// Every thread gets the total (the same sum in the same order); the caller
+// synchronises before red is rewritten.
 __device__ __forceinline__ float block_sum_1024(float v, float* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   const int t = threadIdx.x;
   if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
-  float s = 0.f;
-  if (t == 0)
-    for (int w = 0; w < 16; ++w) s += red[w];
+  float s = red[0];
+#pragma unroll
+  for (int w = 1; w < 16; ++w) s += red[w];
   return s;
 }
 
@@ -69,10 +71,14 @@ __device__ __forceinline__ int reader_tile(int b) {
 // 16-bit intermediates.  With bf16 score storage the intermediate T of a
 // pair is stored as fp16 pairs (4 instead of 8 bytes a value, the same
 // element order, packed into the first half of the pair's slot), each
-// writing workgroup's values with its own power-of-two scale s: the
-// workgroup takes the largest |component| m of its 16384 values, s =
-// 2^(e - 15) with m <= 2^e, so every value is finite and those down to
-// 2^-29 m are normal (about 1.4e-4 relative RMS, well below bf16 storage's
+// writing workgroup's values with its own power-of-two scale s =
+// 2^(e - 15) from a bound m <= 2^e of their components.  The natural side
+// takes the largest |component| of its 16384 values; the frequency side of
+// the forward direction takes the sum of |v| over its 16384 inputs, which
+// bounds every value it writes (each is a sum of some of them times
+// unit-modulus twiddles) and which the 16-bit scores' scale bound reduces
+// anyway.  Every value is finite and those down to 2^-29 m are normal
+// (about 1.4e-4 relative RMS, well below bf16 storage's
 // 1.7e-3; the reconstruction's division by max(M, eps) amplifies errors
 // spread into the spectrum's corners, which rules out bf16 intermediates
 // and keeps fp16 scores on complex64 intermediates).  The scales, one
@@ -138,7 +144,6 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
   __shared__ float red[16];
-  __shared__ float red_t[16];
   const int t = threadIdx.x;
   const int kxb = blockIdx.x & 63, n1 = blockIdx.x >> 6, tile = kxb * 16 + n1;
   const int g = t & 3, s = (t >> 2) & 15, n2 = t >> 6;
@@ -159,8 +164,10 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
     for (int r = 0; r < 16; ++r) pnx[r] = prow[r * 1024];
   }
   const int z = t >> 2, zb = z >> 2, zz = z & 3;
+  static_assert(!T16 || LM == LM_MULBANK, "fp16 intermediates are scaled by the tile's bound sum");
   for (int j = 0; j < a.nb; ++j) {
     float2 v[16];
+    float tile_abs = 0.f;  // sum of |v| over the workgroup's tile
     if constexpr (LM == LM_MULBANK) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = cscale(spec[r], pnx[r]);
@@ -169,12 +176,14 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) pnx[r] = prow[r * 1024];
       }
-      if (a.partial) {  // scale bound of 16-bit storage only
+      if (T16 || a.partial) {  // scale bound of 16-bit storage only
+        // the hardware square root (1 ulp) is ample for a bound that is
+        // rounded up to a power of two
         float asum = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) asum += sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
-        const float tot = block_sum_1024(asum, red);
-        if (t == 0) a.partial[(long long)j * gridDim.x + blockIdx.x] = tot;
+        for (int r = 0; r < 16; ++r) asum += __builtin_amdgcn_sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
+        tile_abs = block_sum_1024(asum, red);
+        if (t == 0 && a.partial) a.partial[(long long)j * gridDim.x + blockIdx.x] = tile_abs;
       }
     } else {
 #pragma unroll
@@ -206,9 +215,10 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
 #pragma unroll
       for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = u[k2];
     } else {
-      // its own LDS words: the next pair's scale-bound sum reuses red before
-      // the next barrier
-      const float sT = tile_scale(u, red_t);
+      // every value of the tile's T is a sum of some of its 16384 values
+      // times unit-modulus twiddles, so sum |v| bounds them all: no
+      // reduction of its own
+      const float sT = t16_scale(tile_abs);
       unsigned int* T = (unsigned int*)a.dst_c + (long long)j * a.dst_stride;
       const float inv = 1.f / sT;  // a power of two: exact
 #pragma unroll
@@ -404,7 +414,9 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
   const int t = threadIdx.x;
-  const int tile = blockIdx.x, k2 = tile >> 6, kxb = tile & 63;
+  // fp16 intermediates: the four readers of a block load 64-byte quarters
+  // of its 128-byte lines, so they run side by side on one XCD (one L2)
+  const int tile = T16 ? reader_tile(blockIdx.x) : blockIdx.x, k2 = tile >> 6, kxb = tile & 63;
   load_twiddles<-1>(a, twl);
   const long long pbase = (long long)(kxb * 16 + k2) << 14;
   const int jb = (SM == SM_ACCUM) ? 0 : blockIdx.y;
