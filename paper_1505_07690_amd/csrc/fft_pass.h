@@ -88,22 +88,26 @@ __device__ __forceinline__ unsigned int bf16_rne(float x) {
 // Score element i as complex float (16-bit pairs times their scale s).  The
 // storage type is a template parameter so that the loads of a pass are not
 // separated by branches and can all be in flight together.
+// A stored 16-bit pair times its scale s.
+template <int DT>
+__device__ __forceinline__ float2 score_value(unsigned int q, float s) {
+  float re, im;
+  if constexpr (DT == OS3D_F16X2) {
+    re = __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
+    im = __half2float(__ushort_as_half((unsigned short)(q >> 16)));
+  } else {
+    re = __uint_as_float((q & 0xffffu) << 16);
+    im = __uint_as_float(q & 0xffff0000u);
+  }
+  return make_float2(re * s, im * s);
+}
+
 template <int DT>
 __device__ __forceinline__ float2 load_score(const void* U, long long i, float s) {
-  if constexpr (DT == OS3D_C64) {
+  if constexpr (DT == OS3D_C64)
     return ((const float2*)U)[i];
-  } else {
-    const unsigned int q = ((const unsigned int*)U)[i];
-    float re, im;
-    if constexpr (DT == OS3D_F16X2) {
-      re = __half2float(__ushort_as_half((unsigned short)(q & 0xffffu)));
-      im = __half2float(__ushort_as_half((unsigned short)(q >> 16)));
-    } else {
-      re = __uint_as_float((q & 0xffffu) << 16);
-      im = __uint_as_float(q & 0xffff0000u);
-    }
-    return make_float2(re * s, im * s);
-  }
+  else
+    return score_value<DT>(((const unsigned int*)U)[i], s);
 }
 
 

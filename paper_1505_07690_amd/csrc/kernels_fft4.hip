@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "fft_pass.h"
 #include "launch.h"
@@ -223,41 +224,19 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
       const float inv = 1.f / sT;  // a power of two: exact
 #pragma unroll
       for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = pack_f16(u[k2], inv);
-      if (t == 0) a.tsc_out[(long long)j * gridDim.x + blockIdx.x] = sT;
+      // at the tile index, so that a reader's 16 writers' scales are adjacent
+      if (t == 0) a.tsc_out[(long long)j * gridDim.x + tile] = sT;
     }
   }
 }
 
 // Natural side of the inverse direction: T tile (k2, zb) -> rows of four z
 // planes.  Step C over n1, then the x DFT (two stages), then the fused store.
-template <int SM, int DT, bool T16 = false>
-__global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
-  __shared__ float2 lds[4 * k4Sub];
-  __shared__ float2 twl[256];
+// v: the thread's 16 values of the tile in T (value q from the writer n1 = q).
+template <int SM, int DT>
+__device__ __forceinline__ void inv_nat_tile(const PassArgs& a, float2* lds, const float2* twl, int j, int k2, int zb,
+                                             float2 (&v)[16]) {
   const int t = threadIdx.x;
-  const int tile = reader_tile(blockIdx.x), k2 = tile >> 6, zb = tile & 63;
-  const int j = blockIdx.y;
-  load_twiddles<1>(a, twl);
-  const long long to = (long long)j * a.src_stride + (long long)(k2 * 16 + (zb >> 2)) * 16 * 4096 + (t >> 4) * 64 +
-                       (zb & 3) * 16 + (t & 15);
-  float2 v[16];
-  if constexpr (!T16) {
-    const float2* T = a.src_c + to;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = T[q * 4096];
-  } else {
-    // value q was written by the frequency-side workgroup (kxb = t / 16, n1 = q)
-    const unsigned int* T = (const unsigned int*)a.src_c + to;
-    const float* sc = a.tsc + (long long)j * 1024 + (t >> 4);
-    unsigned int w[16];
-    float sT[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) w[q] = T[q * 4096];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) sT[q] = sc[q * 64];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = unpack_f16(w[q], sT[q]);
-  }
   dft16(v, kInv);  // over n1 -> k1
   {
     const int g = (t >> 2) & 3, kx = (t >> 4) * 4 + (t & 3);
@@ -284,24 +263,117 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
   store_k<SM, DT, 16>(a, j, row + s, 16, v, dummy);
 }
 
+// Offset of this thread's 16 values of tile (k2, zb) in pair slot j's T.
+__device__ __forceinline__ long long inv_nat_src(const PassArgs& a, int j, int k2, int zb) {
+  const int t = threadIdx.x;
+  return (long long)j * a.src_stride + (long long)(k2 * 16 + (zb >> 2)) * 16 * 4096 + (t >> 4) * 64 + (zb & 3) * 16 +
+         (t & 15);
+}
+
+// Scales of this thread's 16 writers (tiles (t / 16) * 16 + q of the
+// frequency side), adjacent in the scale array.
+__device__ __forceinline__ void inv_nat_scales(const PassArgs& a, int j, float (&sT)[16]) {
+  const float4* sc = (const float4*)(a.tsc + (long long)j * 1024 + (threadIdx.x >> 4) * 16);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 c = sc[q];
+    sT[4 * q] = c.x;
+    sT[4 * q + 1] = c.y;
+    sT[4 * q + 2] = c.z;
+    sT[4 * q + 3] = c.w;
+  }
+}
+
+template <int SM, int DT, bool T16 = false>
+__global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
+  __shared__ float2 lds[4 * k4Sub];
+  __shared__ float2 twl[256];
+  const int tile = reader_tile(blockIdx.x), k2 = tile >> 6, zb = tile & 63;
+  const int j = blockIdx.y;
+  load_twiddles<1>(a, twl);
+  const long long to = inv_nat_src(a, j, k2, zb);
+  float2 v[16];
+  if constexpr (!T16) {
+    const float2* T = a.src_c + to;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = T[q * 4096];
+  } else {
+    const unsigned int* T = (const unsigned int*)a.src_c + to;
+    unsigned int w[16];
+    float sT[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) w[q] = T[q * 4096];
+    inv_nat_scales(a, j, sT);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = unpack_f16(w[q], sT[q]);
+  }
+  inv_nat_tile<SM, DT>(a, lds, twl, j, k2, zb, v);
+}
+
+// The score passes of the bf16 form (the forward's last pass here, the
+// reconstruction's first pass below) are persistent: a workgroup per CU
+// loops over the launch's (pair slot j, block) tasks, task = 1024 j +
+// block in the order of the one-tile-per-workgroup grid, and issues the next
+// task's loads before it transforms the current tile.  A workgroup holds a
+// whole CU's LDS, so with one tile per workgroup each tile's load latency
+// is exposed; fp16 intermediates and 16-bit scores make a tile half the
+// bytes of a complex64 one, which doubles its weight (bf16 form: 1.88 ->
+// 1.58 ms and 1.73 -> 1.52 ms per launch of 40.5 pairs; the complex64
+// passes and those of the fp16 form, whose intermediates are complex64,
+// gained nothing this way and keep one tile per workgroup).  The
+// grid is a multiple of 8, so a task runs on its block's XCD (task mod 8 =
+// block mod 8) and the four readers of a block of T still run side by side.
+template <int DT, bool T16>
+__global__ __launch_bounds__(k4Threads) void k4_inv_nat_scores(PassArgs a) {
+  __shared__ float2 lds[4 * k4Sub];
+  __shared__ float2 twl[256];
+  load_twiddles<1>(a, twl);
+  const int ntask = 1024 * a.nb;
+  using Word = typename std::conditional<T16, unsigned int, float2>::type;
+  Word w[16];
+  float sT[16];
+  auto issue = [&](int task) {
+    const int tile = reader_tile(task & 1023), j = task >> 10;
+    const Word* T = (const Word*)a.src_c + inv_nat_src(a, j, tile >> 6, tile & 63);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) w[q] = T[q * 4096];
+    if constexpr (T16) inv_nat_scales(a, j, sT);
+  };
+  int task = blockIdx.x;
+  if (task < ntask) issue(task);
+  for (; task < ntask; task += gridDim.x) {
+    const int tile = reader_tile(task & 1023), j = task >> 10;
+    float2 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if constexpr (T16)
+        v[q] = unpack_f16(w[q], sT[q]);
+      else
+        v[q] = w[q];
+    }
+    if (task + gridDim.x < ntask) issue(task + gridDim.x);
+    inv_nat_tile<SM_UOUT, DT>(a, lds, twl, j, tile >> 6, tile & 63, v);
+    __syncthreads();  // the tile's LDS is rewritten by the next task
+  }
+}
+
 // Natural side of the forward direction: rows y = n1 + 16 n2 of four z
 // planes -> T.  x DFT (two stages), then step A over n2 with w^(n1 k2).
 // Consecutive workgroups take consecutive n1: sixteen of them read all 256
-// rows of the same four planes.
-template <int LM, int DT, bool T16 = false>
-__global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
-  __shared__ float2 lds[4 * k4Sub];
-  __shared__ float2 twl[256];
-  __shared__ float red[16];
+// rows of the same four planes.  Block wg = 16 zb + n1 of pair slot j; v: the
+// thread's 16 values of row `nat_row(wg)` at x = s + 16 r.
+__device__ __forceinline__ long long fwd_nat_row(int wg) {
   const int t = threadIdx.x;
-  const int zb = blockIdx.x >> 4, n1 = blockIdx.x & 15;
-  const int j = blockIdx.y;
-  load_twiddles<-1>(a, twl);
+  const int zb = wg >> 4, n1 = wg & 15, g = t >> 8, n2 = (t >> 4) & 15;
+  return ((long long)(4 * zb + g) * 256 + (n1 + 16 * n2)) * 256;
+}
+
+template <bool T16>
+__device__ __forceinline__ void fwd_nat_tile(const PassArgs& a, float2* lds, const float2* twl, float* red, int j,
+                                             int wg, float2 (&v)[16]) {
+  const int t = threadIdx.x;
+  const int zb = wg >> 4, n1 = wg & 15;
   const int g = t >> 8, n2 = (t >> 4) & 15, s = t & 15;
-  const long long row = ((long long)(4 * zb + g) * 256 + (n1 + 16 * n2)) * 256;
-  float2 v[16];
-  float asum = 0.f;
-  load_k<LM, DT, 16>(a, j, row + s, 16, v, asum);
   dft16(v, kFwd);
   float2* S = lds + g * k4Sub + n2 * k4LS;
 #pragma unroll
@@ -333,7 +405,66 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
     const float inv = 1.f / sT;  // a power of two: exact
 #pragma unroll
     for (int k2 = 0; k2 < 16; ++k2) T[(long long)k2 * (256 * 4096) + o] = pack_f16(u[k2], inv);
-    if (t == 0) a.tsc_out[(long long)j * gridDim.x + blockIdx.x] = sT;
+    if (t == 0) a.tsc_out[(long long)j * 1024 + wg] = sT;
+  }
+}
+
+template <int LM, int DT, bool T16 = false>
+__global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
+  __shared__ float2 lds[4 * k4Sub];
+  __shared__ float2 twl[256];
+  __shared__ float red[16];
+  const int j = blockIdx.y;
+  load_twiddles<-1>(a, twl);
+  float2 v[16];
+  float asum = 0.f;
+  load_k<LM, DT, 16>(a, j, fwd_nat_row(blockIdx.x) + (threadIdx.x & 15), 16, v, asum);
+  fwd_nat_tile<T16>(a, lds, twl, red, j, blockIdx.x, v);
+}
+
+// The reconstruction's first pass of the bf16 form, persistent (as
+// k4_inv_nat_scores): the next task's two 16-bit score rows are in flight
+// while the current tile is transformed.
+template <int DT, bool T16>
+__global__ __launch_bounds__(k4Threads) void k4_fwd_nat_scores(PassArgs a) {
+  static_assert(DT != OS3D_C64, "16-bit scores");
+  __shared__ float2 lds[4 * k4Sub];
+  __shared__ float2 twl[256];
+  __shared__ float red[16];
+  load_twiddles<-1>(a, twl);
+  const int ntask = 1024 * a.nb;
+  const int s = threadIdx.x & 15;
+  unsigned int qa[16], qb[16];
+  auto issue = [&](int task) {
+    const int j = task >> 10;
+    const long long row = fwd_nat_row(task & 1023) + s;
+    const unsigned int* Ua = (const unsigned int*)a.U + (long long)a.oa[j] * a.V + row;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) qa[r] = Ua[r * 16];
+    const int ib = a.ob[j];
+    if (ib >= 0) {
+      const unsigned int* Ub = (const unsigned int*)a.U + (long long)ib * a.V + row;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) qb[r] = Ub[r * 16];
+    }
+  };
+  int task = blockIdx.x;
+  if (task < ntask) issue(task);
+  for (; task < ntask; task += gridDim.x) {
+    const int j = task >> 10;
+    const int ia = a.oa[j], ib = a.ob[j];
+    float2 v[16];
+    const float sa = a.scales[ia];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = score_value<DT>(qa[r], sa);
+    if (ib >= 0) {
+      const float sb = a.scales[ib];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = cadd(v[r], cconj(score_value<DT>(qb[r], sb)));
+    }
+    if (task + gridDim.x < ntask) issue(task + gridDim.x);
+    fwd_nat_tile<T16>(a, lds, twl, red, j, task & 1023, v);
+    __syncthreads();  // the tile's LDS (and red) are rewritten by the next task
   }
 }
 
@@ -473,6 +604,19 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
   if constexpr (SM == SM_ACCUM) flush_k<16>(a, pbase + t, 1024, acc);
 }
 
+// Workgroups of a persistent score pass: one per CU, rounded down to a
+// multiple of the 8 XCDs, at most one per task.
+static unsigned persistent_grid(long long ntask) {
+  static const int n = [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
+      cus = 256;
+    return cus / 8 * 8;
+  }();
+  return (unsigned)std::min<long long>(ntask, n);
+}
+
 static int check(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -576,7 +720,8 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
         if (dtype == OS3D_C64)
           launch_k((k4_inv_nat<SM_UOUT, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else if (dtype == OS3D_BF16X2)
-          launch_k((k4_inv_nat<SM_UOUT, OS3D_BF16X2, true>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_inv_nat_scores<OS3D_BF16X2, true>), dim3(persistent_grid(1024LL * nb)), dim3(k4Threads), 0,
+                   st, x);
         else
           launch_k((k4_inv_nat<SM_UOUT, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfFwdLast, nor * (double)V * (double)ubytes, 0.0);
@@ -624,7 +769,8 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
         if (dtype == OS3D_C64)
           launch_k((k4_fwd_nat<LM_UIN, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else if (dtype == OS3D_BF16X2)
-          launch_k((k4_fwd_nat<LM_UIN, OS3D_BF16X2, true>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
+          launch_k((k4_fwd_nat_scores<OS3D_BF16X2, true>), dim3(persistent_grid(1024LL * nb)), dim3(k4Threads), 0,
+                   st, x);
         else
           launch_k((k4_fwd_nat<LM_UIN, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfRecFirst, nor * (double)V * (double)ubytes, 0.0);
