@@ -45,19 +45,6 @@ constexpr int k4Sub = 16 * k4LS + 4;  // one sub-problem: 16 lines of 256; the e
 
 __device__ __forceinline__ int pad4(int n) { return n + (n >> 4); }
 
-// Every thread gets the total (the same sum in the same order); the caller
-// synchronises before red is rewritten.
-__device__ __forceinline__ float block_sum_1024(float v, float* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  const int t = threadIdx.x;
-  if ((t & 63) == 0) red[t >> 6] = v;
-  __syncthreads();
-  float s = red[0];
-#pragma unroll
-  for (int w = 1; w < 16; ++w) s += red[w];
-  return s;
-}
-
 // Tile of a natural-side workgroup of the inverse direction.  The four tiles
 // zb = 4 zbh + zbl (zbl = 0..3) read the four 128-byte quarters of the same
 // 512-byte blocks of T; workgroups are dispatched to the eight XCDs in turn
@@ -166,9 +153,13 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
   }
   const int z = t >> 2, zb = z >> 2, zz = z & 3;
   static_assert(!T16 || LM == LM_MULBANK, "fp16 intermediates are scaled by the tile's bound sum");
+  // the scale bound of 16-bit storage (and the fp16 intermediates' scale):
+  // the sum of |v| over the tile, its wave totals passed through LDS at the
+  // first exchange's barrier
+  const bool bound = LM == LM_MULBANK && (T16 || a.partial != nullptr);
   for (int j = 0; j < a.nb; ++j) {
     float2 v[16];
-    float tile_abs = 0.f;  // sum of |v| over the workgroup's tile
+    float wave_abs = 0.f;
     if constexpr (LM == LM_MULBANK) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = cscale(spec[r], pnx[r]);
@@ -177,14 +168,12 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) pnx[r] = prow[r * 1024];
       }
-      if (T16 || a.partial) {  // scale bound of 16-bit storage only
+      if (bound) {
         // the hardware square root (1 ulp) is ample for a bound that is
         // rounded up to a power of two
-        float asum = 0.f;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) asum += __builtin_amdgcn_sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
-        tile_abs = block_sum_1024(asum, red);
-        if (t == 0 && a.partial) a.partial[(long long)j * gridDim.x + blockIdx.x] = tile_abs;
+        for (int r = 0; r < 16; ++r) wave_abs += __builtin_amdgcn_sqrtf(v[r].x * v[r].x + v[r].y * v[r].y);
+        for (int o = 32; o > 0; o >>= 1) wave_abs += __shfl_xor(wave_abs, o);
       }
     } else {
 #pragma unroll
@@ -192,10 +181,19 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_phi(PassArgs a) {
     }
     dft16(v, kInv);
     float2* S = lds + g * k4Sub + n2 * k4LS;
-    if (j > 0) __syncthreads();  // the previous pair's step-A reads are done
+    // the previous pair's step-A reads (and its reads of red) are done
+    if (j > 0) __syncthreads();
 #pragma unroll
     for (int r = 0; r < 16; ++r) S[pad4(s * 16 + r)] = v[r];
+    if (bound && (t & 63) == 0) red[t >> 6] = wave_abs;
     __syncthreads();
+    float tile_abs = 0.f;  // sum of |v| over the workgroup's tile, every thread
+    if (bound) {
+      tile_abs = red[0];
+#pragma unroll
+      for (int w = 1; w < 16; ++w) tile_abs += red[w];
+      if (t == 0 && a.partial) a.partial[(long long)j * gridDim.x + blockIdx.x] = tile_abs;
+    }
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = S[pad4(s + 16 * r)];
 #pragma unroll
