@@ -553,32 +553,37 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_phi(PassArgs a) {
   float2 acc[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = make_float2(0.f, 0.f);
+  const long long tb = (long long)(k2 * 16 + (kxb >> 2)) * 16 * 4096 + (t >> 4) * 64 + (kxb & 3) * 16 + (t & 15);
+  unsigned int wn[16];  // fp16 intermediates: the next pair's words, in flight during this pair
+  if constexpr (T16) {
+    const unsigned int* T = (const unsigned int*)a.src_c + (long long)jb * a.src_stride + tb;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) wn[q] = ldnt(T + q * 4096);
+  }
   for (int j = jb; j < je; ++j) {
-    const long long to = (long long)j * a.src_stride + (long long)(k2 * 16 + (kxb >> 2)) * 16 * 4096 +
-                         (t >> 4) * 64 + (kxb & 3) * 16 + (t & 15);
     float2 v[16];
     if constexpr (!T16) {
-      const float2* T = a.src_c + to;
+      const float2* T = a.src_c + (long long)j * a.src_stride + tb;
 #pragma unroll
       for (int q = 0; q < 16; ++q) v[q] = ldnt(T + q * 4096);
     } else {
       // value q was written by the natural-side workgroup (zb = t / 16, n1 = q)
-      const unsigned int* T = (const unsigned int*)a.src_c + to;
       const float* sc = a.tsc + (long long)j * 1024 + (t >> 4) * 16;
-      unsigned int w[16];
-      float sT[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) w[q] = ldnt(T + q * 4096);
-#pragma unroll
-      for (int q = 0; q < 16; ++q) sT[q] = sc[q];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = unpack_f16(w[q], sT[q]);
+      for (int q = 0; q < 16; ++q) v[q] = unpack_f16(wn[q], sc[q]);
     }
     dft16(v, kFwd);  // over n1 -> k1
     {
       const int g = t & 3, z = t >> 2;
 #pragma unroll
       for (int k1 = 0; k1 < 16; ++k1) lds[g * k4Sub + k1 * k4LS + pad4(z)] = v[k1];
+    }
+    if constexpr (T16) {
+      if (j + 1 < je) {
+        const unsigned int* T = (const unsigned int*)a.src_c + (long long)(j + 1) * a.src_stride + tb;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) wn[q] = ldnt(T + q * 4096);
+      }
     }
     __syncthreads();
     const int g = t & 3, s = (t >> 2) & 15, k1 = t >> 6;
