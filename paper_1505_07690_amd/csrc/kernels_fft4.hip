@@ -29,7 +29,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <type_traits>
 
 #include "fft_pass.h"
 #include "launch.h"
@@ -321,21 +320,19 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat(PassArgs a) {
 // gained nothing this way and keep one tile per workgroup).  The
 // grid is a multiple of 8, so a task runs on its block's XCD (task mod 8 =
 // block mod 8) and the four readers of a block of T still run side by side.
-template <int DT, bool T16>
 __global__ __launch_bounds__(k4Threads) void k4_inv_nat_scores(PassArgs a) {
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
   load_twiddles<1>(a, twl);
   const int ntask = 1024 * a.nb;
-  using Word = typename std::conditional<T16, unsigned int, float2>::type;
-  Word w[16];
+  unsigned int w[16];
   float sT[16];
   auto issue = [&](int task) {
     const int tile = reader_tile(task & 1023), j = task >> 10;
-    const Word* T = (const Word*)a.src_c + inv_nat_src(a, j, tile >> 6, tile & 63);
+    const unsigned int* T = (const unsigned int*)a.src_c + inv_nat_src(a, j, tile >> 6, tile & 63);
 #pragma unroll
     for (int q = 0; q < 16; ++q) w[q] = T[q * 4096];
-    if constexpr (T16) inv_nat_scales(a, j, sT);
+    inv_nat_scales(a, j, sT);
   };
   int task = blockIdx.x;
   if (task < ntask) issue(task);
@@ -343,14 +340,9 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat_scores(PassArgs a) {
     const int tile = reader_tile(task & 1023), j = task >> 10;
     float2 v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      if constexpr (T16)
-        v[q] = unpack_f16(w[q], sT[q]);
-      else
-        v[q] = w[q];
-    }
+    for (int q = 0; q < 16; ++q) v[q] = unpack_f16(w[q], sT[q]);
     if (task + gridDim.x < ntask) issue(task + gridDim.x);
-    inv_nat_tile<SM_UOUT, DT>(a, lds, twl, j, tile >> 6, tile & 63, v);
+    inv_nat_tile<SM_UOUT, OS3D_BF16X2>(a, lds, twl, j, tile >> 6, tile & 63, v);
     __syncthreads();  // the tile's LDS is rewritten by the next task
   }
 }
@@ -359,7 +351,7 @@ __global__ __launch_bounds__(k4Threads) void k4_inv_nat_scores(PassArgs a) {
 // planes -> T.  x DFT (two stages), then step A over n2 with w^(n1 k2).
 // Consecutive workgroups take consecutive n1: sixteen of them read all 256
 // rows of the same four planes.  Block wg = 16 zb + n1 of pair slot j; v: the
-// thread's 16 values of row `nat_row(wg)` at x = s + 16 r.
+// thread's 16 values of row `fwd_nat_row(wg)` at x = s + 16 r.
 __device__ __forceinline__ long long fwd_nat_row(int wg) {
   const int t = threadIdx.x;
   const int zb = wg >> 4, n1 = wg & 15, g = t >> 8, n2 = (t >> 4) & 15;
@@ -423,9 +415,7 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat(PassArgs a) {
 // The reconstruction's first pass of the bf16 form, persistent (as
 // k4_inv_nat_scores): the next task's two 16-bit score rows are in flight
 // while the current tile is transformed.
-template <int DT, bool T16>
 __global__ __launch_bounds__(k4Threads) void k4_fwd_nat_scores(PassArgs a) {
-  static_assert(DT != OS3D_C64, "16-bit scores");
   __shared__ float2 lds[4 * k4Sub];
   __shared__ float2 twl[256];
   __shared__ float red[16];
@@ -454,14 +444,14 @@ __global__ __launch_bounds__(k4Threads) void k4_fwd_nat_scores(PassArgs a) {
     float2 v[16];
     const float sa = a.scales[ia];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = score_value<DT>(qa[r], sa);
+    for (int r = 0; r < 16; ++r) v[r] = score_value<OS3D_BF16X2>(qa[r], sa);
     if (ib >= 0) {
       const float sb = a.scales[ib];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = cadd(v[r], cconj(score_value<DT>(qb[r], sb)));
+      for (int r = 0; r < 16; ++r) v[r] = cadd(v[r], cconj(score_value<OS3D_BF16X2>(qb[r], sb)));
     }
     if (task + gridDim.x < ntask) issue(task + gridDim.x);
-    fwd_nat_tile<T16>(a, lds, twl, red, j, task & 1023, v);
+    fwd_nat_tile<true>(a, lds, twl, red, j, task & 1023, v);
     __syncthreads();  // the tile's LDS (and red) are rewritten by the next task
   }
 }
@@ -723,8 +713,7 @@ int forward4(const os3d_bank* b, const float* f, int batch, void* U, int dtype, 
         if (dtype == OS3D_C64)
           launch_k((k4_inv_nat<SM_UOUT, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else if (dtype == OS3D_BF16X2)
-          launch_k((k4_inv_nat_scores<OS3D_BF16X2, true>), dim3(persistent_grid(1024LL * nb)), dim3(k4Threads), 0,
-                   st, x);
+          launch_k(k4_inv_nat_scores, dim3(persistent_grid(1024LL * nb)), dim3(k4Threads), 0, st, x);
         else
           launch_k((k4_inv_nat<SM_UOUT, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfFwdLast, nor * (double)V * (double)ubytes, 0.0);
@@ -772,8 +761,7 @@ int reduce4(const os3d_bank* b, const void* U, int dtype, const float* scales, i
         if (dtype == OS3D_C64)
           launch_k((k4_fwd_nat<LM_UIN, OS3D_C64>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         else if (dtype == OS3D_BF16X2)
-          launch_k((k4_fwd_nat_scores<OS3D_BF16X2, true>), dim3(persistent_grid(1024LL * nb)), dim3(k4Threads), 0,
-                   st, x);
+          launch_k(k4_fwd_nat_scores, dim3(persistent_grid(1024LL * nb)), dim3(k4Threads), 0, st, x);
         else
           launch_k((k4_fwd_nat<LM_UIN, OS3D_F16X2>), dim3(1024, nb), dim3(k4Threads), 0, st, x);
         prof_stop(tok, st, kProfRecFirst, nor * (double)V * (double)ubytes, 0.0);
