@@ -2,7 +2,8 @@
 bench.py times (the two-pass 256^3 path and the three-pass 128^3 path).
 
 * 256^3 with the 12 icosahedron orientations: everything against the FP64
-  oracle (bank, M, kappa, forward, adjoint, reconstruction, 16-bit storage).
+  oracle (bank, M, kappa, forward, adjoint, reconstruction, 16-bit storage);
+  the same with the tetrahedron's 4 orientations, which have no antipodes.
 * 128^3 x 42 orientations, L = 16 (the mid-size workload): everything against
   the oracle.
 * 256^3 x 162 orientations, L = 24 (the headline workload): properties that
@@ -96,6 +97,53 @@ def test_full_size_against_oracle(torch, shape, level, L):
         ra = os3d.reconstruct_approx(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
         assert rel(ra, approx_o) < bound
         del Uq
+
+
+def test_full_size_unpaired_against_oracle(torch):
+    """256^3 with the tetrahedron's 4 orientations, which has no antipodes:
+    the pair path is off and every slot of the two-pass kernels takes one
+    orientation (no partner), in every storage mode, against the oracle."""
+    from paper_1505_07690_amd import os3d
+    shape = (256, 256, 256)
+    n = inputs.platonic_orientations("tetrahedron")
+    p = _params(4, len(n))
+    vol = inputs.tubes(shape, 10, (1.0, 3.0), 0.2, 0, 41)
+    ob = O.build_bank(shape, n, p)
+    gb = os3d.Bank(shape, n, p)
+    assert not gb.paired and gb.n_unique == 4
+    assert rel(np.stack([gb.psi(i).cpu().numpy() for i in range(4)]), ob["psi_hat"]) < TOL
+    assert rel(gb.M().cpu().numpy(), ob["M"]) < TOL
+    f = torch.from_numpy(vol).cuda()
+    U, _ = os3d.forward(f, gb)
+    Uo = O.forward(vol.astype(np.float64), ob)
+    assert rel(U.cpu().numpy(), Uo) < TOL
+    del U
+    Ur = _complex_scores(4, shape, 6)
+    Ug = torch.from_numpy(Ur).cuda()
+    rec = os3d.reconstruct(Ug, gb).cpu().numpy()
+    adj = os3d.adjoint(Ug, gb).cpu().numpy()
+    del Ug
+    X = O.os3d_oracle._orientation_sum(Ur.astype(np.complex128), ob)
+    assert rel(rec, np.real(O.idft3(X / np.maximum(ob["M"], p.eps)))) < TOL
+    assert rel(adj, np.real(O.idft3(X))) < TOL
+    del X, Ur
+    # 16-bit storage: the scores within the storage bounds; the
+    # reconstruction against the oracle's reconstruction of the same
+    # dequantised scores, which isolates the kernels from the storage error.
+    # (With 4 orientations M is small over much of the spectrum and the
+    # division by max(M, eps) amplifies the storage error itself past the
+    # reconstruction bounds of the configured sets: bf16 4.6e-3, fp16 5.7e-4
+    # also through complex64 intermediates.)  fp16 scores keep complex64
+    # intermediates (FP32 tolerance); bf16 ones use fp16 intermediates, whose
+    # rounding adds about 4e-4 here after the same amplification.
+    for fmt, bound_u, bound_rec in (("bf16", 4e-3, 1e-3), ("fp16", 5e-4, TOL)):
+        Uq, sc = os3d.forward(f, gb, dtype=fmt)
+        Ud = os3d.unpack16(Uq, sc, fmt).cpu().numpy()
+        assert rel(Ud, Uo) < bound_u
+        rq = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
+        del Uq
+        assert rel(rq, O.reconstruct(Ud.astype(np.complex128), ob)) < bound_rec
+        del Ud
 
 
 @pytest.fixture(scope="module")
