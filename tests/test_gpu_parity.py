@@ -103,6 +103,11 @@ CASES = {
                        inputs.tubes((10, 8, 12), 2, 1.2, 0.1, 0, 26)),
     # the two non-power-of-two shapes of the serving workload (12 orientations
     # to bound the oracle's time): radix 3 and 5 on the three-pass path, and
+    # sets without antipodes on the whole-plane path (every pair slot unpaired)
+    "plane128_tetra": lambda: ((12, 128, 128), inputs.platonic_orientations("tetrahedron"), _oracle_params(6, 4),
+                               inputs.tubes((12, 128, 128), 3, 1.5, 0.1, 0, 51)),
+    "plane64_rand5": lambda: ((16, 64, 64), _random_orients(5, 53), _oracle_params(8, 5),
+                              inputs.tubes((16, 64, 64), 3, 1.5, 0.1, 0, 52)),
     # a z axis of 160 under 128 x 128 planes on the plane path
     "serve96x80x64": lambda: ((96, 80, 64), inputs.icosahedral_orientations(0), _oracle_params(24, 12),
                               inputs.tubes((96, 80, 64), 12, (1.0, 3.0), 0.2, 0, 27)),
@@ -142,7 +147,8 @@ def test_bank_and_M_parity(case):
     assert rel(psi, ob["psi_hat"]) < TOL
     assert rel(gb.M().cpu().numpy(), ob["M"]) < TOL
     assert abs(gb.kappa - ob["kappa"]) < 1e-6 * ob["kappa"]
-    unpaired = ("unpaired_plate", "tetra", "single", "rand60", "rand40", "rand70", "rand110")
+    unpaired = ("unpaired_plate", "tetra", "single", "rand60", "rand40", "rand70", "rand110", "plane128_tetra",
+                "plane64_rand5")
     assert gb.paired == (case["name"] not in unpaired)
 
 
@@ -271,6 +277,28 @@ def test_reduced_precision_storage(torch_dev, fmt, bound, shape):
     j = np.argmin(d, axis=1)
     Uc = os3d.unpack16(Uq, sc, fmt)
     assert torch_dev.equal(Uc[j], torch_dev.conj(Uc).resolve_conj())
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+@pytest.mark.parametrize("shape", [(12, 128, 128), (16, 64, 64)], ids=["plane128", "plane64"])
+def test_reduced_precision_unpaired_plane(torch_dev, fmt, shape):
+    """16-bit storage on the whole-plane path with a set without antipodes
+    (the tetrahedron): the scores within the storage bound of the FP64
+    oracle's, and the reconstruction against the oracle's reconstruction of
+    the same dequantised scores — the plane path keeps complex64
+    intermediates, so within the FP32 tolerance.  (With 4 orientations the
+    division by max(M, eps) amplifies the storage error itself, so the
+    reconstruction is not compared with the oracle's from exact scores.)"""
+    from paper_1505_07690_amd import os3d
+    n = inputs.platonic_orientations("tetrahedron")
+    ob, gb, f = _case(shape, n, _oracle_params(6, 4), inputs.tubes(shape, 3, 1.5, 0.1, 0, 54))
+    assert not gb.paired
+    Uq, sc = os3d.forward(f, gb, dtype=fmt)
+    Ud = os3d.unpack16(Uq, sc, fmt).cpu().numpy()
+    Uo = O.forward(f.cpu().numpy().astype(np.float64), ob)
+    assert rel(Ud, Uo) < {"bf16": 4e-3, "fp16": 5e-4}[fmt]
+    rec = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
+    assert rel(rec, O.reconstruct(Ud.astype(np.complex128), ob)) < TOL
 
 
 def test_approximate_reconstruction_parity(case):
