@@ -102,7 +102,9 @@ def test_full_size_against_oracle(torch, shape, level, L):
 def test_full_size_unpaired_against_oracle(torch):
     """256^3 with the tetrahedron's 4 orientations, which has no antipodes:
     the pair path is off and every slot of the two-pass kernels takes one
-    orientation (no partner), in every storage mode, against the oracle."""
+    orientation (no partner): forward, reconstruction, adjoint, processing
+    via scores and the approximate reconstruction, in every storage mode,
+    against the oracle."""
     from paper_1505_07690_amd import os3d
     shape = (256, 256, 256)
     n = inputs.platonic_orientations("tetrahedron")
@@ -127,6 +129,13 @@ def test_full_size_unpaired_against_oracle(torch):
     assert rel(rec, np.real(O.idft3(X / np.maximum(ob["M"], p.eps)))) < TOL
     assert rel(adj, np.real(O.idft3(X))) < TOL
     del X, Ur
+    # processing via scores (Eq. 23) and the approximate reconstruction (Eq. 6)
+    gp = os3d.process(f, gb, "soft_threshold", 1.5).cpu().numpy()
+    assert rel(gp, O.reconstruct(O.soft_threshold(Uo, 1.5), ob)) < TOL
+    del gp
+    Ug = torch.from_numpy(np.ascontiguousarray(Uo, dtype=np.complex64)).cuda()
+    assert rel(os3d.reconstruct_approx(Ug, gb).cpu().numpy(), O.reconstruct_approx(Uo, ob)) < TOL
+    del Ug
     # 16-bit storage: the scores within the storage bounds; the
     # reconstruction against the oracle's reconstruction of the same
     # dequantised scores, which isolates the kernels from the storage error.
