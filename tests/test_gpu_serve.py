@@ -57,6 +57,27 @@ def test_alone_equals_mix(torch):
         assert torch.equal(o, _alone(torch, v, n, L, op, dt)), (sh, n, L, op, dt)
 
 
+def test_16bit_jobs_at_256cube_on_concurrent_slots(torch):
+    """bf16 and fp16 jobs on the two-pass 256^3 path (fp16 intermediates and
+    persistent score passes for bf16) running on two slots at once, next to
+    a complex64 one: every served result equals the same job run alone."""
+    from paper_1505_07690_amd.serve import Server
+    jobs = [((256, 256, 256), 42, 16, "reconstruct", "bf16"),
+            ((256, 256, 256), 42, 16, "reconstruct", "c64"),
+            ((256, 256, 256), 42, 16, "reconstruct", "bf16"),
+            ((256, 256, 256), 42, 16, "reconstruct", "fp16"),
+            ((128, 128, 128), 42, 16, "reconstruct", "bf16")]
+    vols = [inputs.tubes_device(sh, 12, (1.0, 3.0), 0.2, 0, 200 + i) for i, (sh, *_) in enumerate(jobs)]
+    torch.cuda.synchronize()
+    with Server(64 << 30, n_slots=2, max_batch=1) as s:
+        futs = [s.submit(v, n, L, op=op, dtype=dt) for v, (sh, n, L, op, dt) in zip(vols, jobs)]
+        outs = [f.result(timeout=120) for f in futs]
+        st = s.stats()
+    assert st["ok"] == len(jobs)
+    for v, o, (sh, n, L, op, dt) in zip(vols, outs, jobs):
+        assert torch.equal(o, _alone(torch, v, n, L, op, dt)), (sh, n, L, op, dt)
+
+
 def test_served_job_matches_oracle(torch):
     from paper_1505_07690_amd.serve import Server
     shape = (32, 32, 32)
