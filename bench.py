@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 F16_MATRIX_TFLOPS = 2500.0    # MI355X dense fp16 matrix peak
 FP32_VECTOR_TFLOPS = 157.3   # MI355X FP32 vector peak (packed FP32 counted)
+FP32_MATRIX_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
 
 WORKLOADS = {
     # name: (config key of the volume recipe, human label)
@@ -80,6 +81,16 @@ def parse():
 # 11 for the score map: 1/V scale, |u|^2, log2, exp2, the pair factor and the
 # complex scale).
 PHI_FLOPS = 11
+
+
+def step_flops(V, No, paired):
+    """Algorithmic flops of one forward + reconstruction of one volume: per
+    voxel-orientation 5 log2 V for the transforms (an inverse DFT per
+    orientation pair in the forward, a forward DFT per pair in the
+    reconstruction; twice that without antipodal pairs) plus 6 for the
+    spectral multiply and the orientation sum (126 at 256^3 with pairs)."""
+    per_vo = 5 * math.log2(V) * (1 if paired else 2) + 6
+    return per_vo * V * No
 
 
 def process_flops_per_pair_voxel(shape, kernel):
@@ -336,11 +347,15 @@ def main():
         "roofline": roofline,
         "step_roofline": {"alg_bytes_per_step": step_bytes, "achieved_GBs": step_bytes / (ms_per_step / 1e3) / 1e9,
                           "frac": step_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS},
+        # the same step's transform arithmetic against the FP32 vector peak
+        "step_flops": flops_figures(step_flops(V, No, bank.paired), ms_per_step) if args.op == "reconstruct" else None,
         # the contraction's FP32-accurate flops run as three fp16 MFMA
         # products per term (hi hi, hi lo, lo hi): its share of the dense
         # fp16 MFMA peak counts all three
+        # (its FP32-accurate rate also exceeds the dense FP32 matrix peak)
         "bank_build": {"synth_ms": bank_ms, "alg_tflops": bank_flops / (bank_ms / 1e3) / 1e12 if bank_ms else None,
-                       "mfma_f16_frac": 3 * bank_flops / (bank_ms / 1e3) / 1e12 / F16_MATRIX_TFLOPS if bank_ms else None},
+                       "mfma_f16_frac": 3 * bank_flops / (bank_ms / 1e3) / 1e12 / F16_MATRIX_TFLOPS if bank_ms else None,
+                       "fp32_matrix_frac": bank_flops / (bank_ms / 1e3) / 1e12 / FP32_MATRIX_TFLOPS if bank_ms else None},
         "kernels_last_warmup_step": breakdown,
         "wall_s_timed": wall,
         "source_digest": digest,
@@ -423,6 +438,11 @@ def bank_total_ms(shape, orients, p):
     return dt
 
 
+def flops_figures(flops, ms):
+    tf = flops / (ms / 1e3) / 1e12
+    return {"alg_flops_per_step": flops, "achieved_tflops": tf, "fp32_vector_frac": tf / FP32_VECTOR_TFLOPS}
+
+
 def storage_form(bank, fb, dtype, ws, args, V, No):
     """The same step with 16-bit score storage: timing and its scores and
     reconstruction (kept on the device for the precision table)."""
@@ -443,7 +463,8 @@ def storage_form(bank, fb, dtype, ws, args, V, No):
     alg = V * No * 2 * 4 + 8 * V
     return ({"ms_per_step": ms, "p50_ms": float(np.percentile(per, 50)), "p99_ms": float(np.percentile(per, 99)),
              "value": V * No / (ms / 1e3), "unit": "voxel-orientations/s",
-             "step_roofline_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_step": alg},
+             "step_roofline_frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_step": alg,
+             "step_flops": flops_figures(step_flops(V, No, bank.paired), ms)},
             (Uq[0], sc[0], rq[0]))
 
 

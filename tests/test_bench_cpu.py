@@ -51,3 +51,18 @@ def test_processing_flop_counts():
     assert b.process_flops_per_pair_voxel((128, 128, 128), "fwd_last_store_scores") == 2 * 70 + b.PHI_FLOPS
     assert b.process_flops_per_pair_voxel((128, 128, 128), "rec_last_accumulate") == 5 * 7 + 4
     assert b.process_flops_per_pair_voxel((48, 40, 32), "fwd_last_store_scores") is None
+
+
+def test_step_flop_counts():
+    """Forward + reconstruction: 5 log2 V flops per voxel-orientation for the
+    transforms with antipodal pairs (one DFT per pair in each direction),
+    twice that without, plus 6 for the multiply and the orientation sum:
+    126 and 246 at 256^3; the FP32 fraction is the achieved rate over
+    157.3 TFLOP/s."""
+    b = _bench()
+    V = 1 << 24
+    assert b.step_flops(V, 162, True) == 126 * V * 162
+    assert b.step_flops(V, 162, False) == 246 * V * 162
+    assert b.step_flops(1 << 21, 42, True) == (5 * 21 + 6) * (1 << 21) * 42
+    f = b.flops_figures(157.3e12 * 2e-3, 2.0)  # 2 ms of work at the peak rate
+    assert abs(f["achieved_tflops"] - 157.3) < 1e-9 and abs(f["fp32_vector_frac"] - 1.0) < 1e-12
