@@ -449,6 +449,10 @@ __device__ __forceinline__ float approx_re(unsigned int q) {
     return __uint_as_float((q & 0xffffu) << 16);
 }
 
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+
 template <int DT, int VPT>
 __global__ __launch_bounds__(256) void k_approx_reconstruct(const void* U, const float* scales, int n_orients,
                                                             long long V, float inv_norm, float* out) {
@@ -459,9 +463,9 @@ __global__ __launch_bounds__(256) void k_approx_reconstruct(const void* U, const
     for (int i = 0; i < n_orients; ++i) {
       const long long e = (long long)i * V + p;
       if constexpr (DT == OS3D_C64)
-        acc += ((const float2*)U)[e].x;
+        acc += __builtin_nontemporal_load((const nt_f2*)U + e).x;
       else
-        acc += approx_re<DT>(((const unsigned int*)U)[e]) * scales[i];
+        acc += approx_re<DT>(__builtin_nontemporal_load((const unsigned int*)U + e)) * scales[i];
     }
     out[p] = acc * inv_norm;
   } else {
@@ -471,15 +475,16 @@ __global__ __launch_bounds__(256) void k_approx_reconstruct(const void* U, const
 #pragma unroll 4
     for (int i = 0; i < n_orients; ++i) {
       const long long e = (long long)i * V + p;
+      // every score is read once: non-temporal loads
       if constexpr (DT == OS3D_C64) {
         static_assert(VPT == 2, "complex64 scores: two per 16-byte load");
-        const float4 w = *(const float4*)((const float2*)U + e);
+        const nt_f4 w = __builtin_nontemporal_load((const nt_f4*)((const float2*)U + e));
         acc[0] += w.x;
         acc[1] += w.z;
       } else {
         static_assert(VPT == 4, "16-bit scores: four per 16-byte load");
         const float sc = scales[i];
-        const uint4 w = *(const uint4*)((const unsigned int*)U + e);
+        const nt_u4 w = __builtin_nontemporal_load((const nt_u4*)((const unsigned int*)U + e));
         acc[0] += approx_re<DT>(w.x) * sc;
         acc[1] += approx_re<DT>(w.y) * sc;
         acc[2] += approx_re<DT>(w.z) * sc;
