@@ -488,3 +488,27 @@ def test_reserve_scratch_sizes_every_slot_before_a_burst():
             f.result(timeout=5)
         assert ex.slot_bytes == grown and s._scratch_acc == [want] * 3
     assert s._used == 0
+
+
+def test_reserve_scratch_edges():
+    """reserve_scratch with an executor that keeps no scratch returns 0;
+    keys that are not cached reserve nothing; a budget with room for only
+    some slots grows only those (the rest stay as they were, the budget is
+    never exceeded); a closed server refuses."""
+    with Server(1 << 30, n_slots=2, executor=FakeExecutor(2)) as s:
+        assert s.reserve_scratch() == 0
+    ex = ScratchExecutor(3, run_s=0.001)
+    key = ((8, 8, 8), 42, 8)
+    bank = ex.bank_bytes(key)
+    half = ex.job_bytes(key, FakeBank(key), 1, "reconstruct", "c64") // 2
+    # the bank, one slot's scratch from a first job and room for one more
+    s = Server(bank + 2 * half + half // 2, n_slots=3, max_batch=1, executor=ex)
+    s.submit(vol((8, 8, 8), 0), 42, 8).result(timeout=5)
+    assert s.reserve_scratch(keys=[((8, 8, 16), 42, 8)]) == 0  # not cached
+    assert s.reserve_scratch() == half
+    assert sorted(s._scratch_acc) == [0, half, half] and sorted(ex.slot_bytes) == [0, half, half]
+    assert s._used == bank + 2 * half <= s.budget
+    s.close()
+    assert s._used == 0
+    with pytest.raises(RuntimeError):
+        s.reserve_scratch()
