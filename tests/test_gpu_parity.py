@@ -394,3 +394,63 @@ def test_three_pass_path_on_plane_shapes(torch_dev, monkeypatch):
         U, _ = os3d.forward(f, gb)
         assert rel(U.cpu().numpy(), Uo) < TOL
         assert rel(os3d.reconstruct(U, gb).cpu().numpy(), ro) < TOL
+
+
+def _smooth235(m):
+    for q in (2, 3, 5):
+        while m % q == 0:
+            m //= q
+    return m == 1
+
+
+def _sweep_case(seed):
+    """A seeded draw outside the hand-picked cases: each axis one of the
+    supported lengths (prime factors 2, 3, 5) from 2 to 48, odd or even, an
+    orientation set with or without antipodes, L from 0 to 12, bank variant
+    cake or plate."""
+    rng = np.random.default_rng(1000 + seed)
+    lengths = [m for m in range(2, 49) if _smooth235(m)]
+    shape = tuple(int(lengths[i]) for i in rng.integers(0, len(lengths), 3))
+    if max(shape) < 4:  # the normalisation band needs one axis of 4 or more
+        shape = (shape[0], shape[1], 4)
+    kind = int(rng.integers(4))
+    if kind == 0:
+        n = inputs.icosahedral_orientations(0)
+    elif kind == 1:
+        n = inputs.platonic_orientations("octahedron")
+    elif kind == 2:
+        n = inputs.platonic_orientations("tetrahedron")
+    else:
+        n = _random_orients(int(rng.integers(1, 21)), 2000 + seed)
+    L = int(rng.integers(0, 13))
+    variant = "plate" if rng.random() < 0.25 else "cake"
+    return shape, n, _oracle_params(L, len(n), variant)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_seeded_shape_sweep(torch_dev, seed):
+    """Bank, M, forward and reconstruction of a general complex score
+    against the oracle for a seeded draw of grid, orientation set, L and
+    variant; then 16-bit storage (bf16 for even seeds, fp16 for odd): the
+    scores within the storage bound, their reconstruction against the
+    oracle's reconstruction of the same dequantised scores (complex64
+    intermediates on these paths: the FP32 tolerance)."""
+    from paper_1505_07690_amd import os3d
+    shape, n, p = _sweep_case(seed)
+    vol = inputs.tubes(shape, 2, 1.2, 0.1, 0, 3000 + seed)
+    ob, gb, f = _case(shape, n, p, vol)
+    psi = np.stack([gb.psi(i).cpu().numpy() for i in range(len(n))])
+    assert rel(psi, ob["psi_hat"]) < TOL, (shape, len(n), p.L)
+    assert rel(gb.M().cpu().numpy(), ob["M"]) < TOL
+    U, _ = os3d.forward(f, gb)
+    assert rel(U.cpu().numpy(), O.forward(vol.astype(np.float64), ob)) < TOL, (shape, len(n), p.L)
+    rng = np.random.default_rng(seed)
+    Un = (rng.standard_normal((len(n),) + shape) + 1j * rng.standard_normal((len(n),) + shape)).astype(np.complex64)
+    rec = os3d.reconstruct(torch_dev.from_numpy(Un).cuda(), gb).cpu().numpy()
+    assert rel(rec, O.reconstruct(Un.astype(np.complex128), ob)) < TOL, (shape, len(n), p.L)
+    fmt = "bf16" if seed % 2 == 0 else "fp16"
+    Uq, sc = os3d.forward(f, gb, dtype=fmt)
+    Ud = os3d.unpack16(Uq, sc, fmt).cpu().numpy()
+    assert rel(Ud, O.forward(vol.astype(np.float64), ob)) < {"bf16": 4e-3, "fp16": 5e-4}[fmt], (shape, fmt)
+    rq = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
+    assert rel(rq, O.reconstruct(Ud.astype(np.complex128), ob)) < TOL, (shape, fmt)
