@@ -454,3 +454,35 @@ def test_seeded_shape_sweep(torch_dev, seed):
     assert rel(Ud, O.forward(vol.astype(np.float64), ob)) < {"bf16": 4e-3, "fp16": 5e-4}[fmt], (shape, fmt)
     rq = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
     assert rel(rq, O.reconstruct(Ud.astype(np.complex128), ob)) < TOL, (shape, fmt)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_seeded_plane_sweep(torch_dev, seed):
+    """The whole-plane path (64^2 or 128^2 planes) for seeded draws of the z
+    length, orientation set and L: bank, forward and reconstruction of a
+    general complex score against the oracle, and 16-bit storage as in the
+    grid sweep."""
+    from paper_1505_07690_amd import os3d
+    rng = np.random.default_rng(5000 + seed)
+    lengths = [m for m in range(2, 49) if _smooth235(m)]
+    npl = (64, 128)[int(rng.integers(2))]
+    shape = (int(lengths[int(rng.integers(len(lengths)))]), npl, npl)
+    n = (inputs.icosahedral_orientations(0) if rng.random() < 0.5
+         else _random_orients(int(rng.integers(1, 9)), 6000 + seed))
+    p = _oracle_params(int(rng.integers(0, 13)), len(n))
+    vol = inputs.tubes(shape, 2, 1.5, 0.1, 0, 7000 + seed)
+    ob, gb, f = _case(shape, n, p, vol)
+    assert rel(np.stack([gb.psi(i).cpu().numpy() for i in range(len(n))]), ob["psi_hat"]) < TOL
+    Uo = O.forward(vol.astype(np.float64), ob)
+    U, _ = os3d.forward(f, gb)
+    assert rel(U.cpu().numpy(), Uo) < TOL, (shape, len(n), p.L)
+    del U
+    Un = (rng.standard_normal((len(n),) + shape) + 1j * rng.standard_normal((len(n),) + shape)).astype(np.complex64)
+    rec = os3d.reconstruct(torch_dev.from_numpy(Un).cuda(), gb).cpu().numpy()
+    assert rel(rec, O.reconstruct(Un.astype(np.complex128), ob)) < TOL, (shape, len(n), p.L)
+    fmt = "bf16" if seed % 2 == 0 else "fp16"
+    Uq, sc = os3d.forward(f, gb, dtype=fmt)
+    Ud = os3d.unpack16(Uq, sc, fmt).cpu().numpy()
+    assert rel(Ud, Uo) < {"bf16": 4e-3, "fp16": 5e-4}[fmt], (shape, fmt)
+    rq = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
+    assert rel(rq, O.reconstruct(Ud.astype(np.complex128), ob)) < TOL, (shape, fmt)
