@@ -429,9 +429,10 @@ def _sweep_case(seed):
 
 @pytest.mark.parametrize("seed", range(24))
 def test_seeded_shape_sweep(torch_dev, seed):
-    """Bank, M, forward and reconstruction of a general complex score
-    against the oracle for a seeded draw of grid, orientation set, L and
-    variant; then 16-bit storage (bf16 for even seeds, fp16 for odd): the
+    """Bank, M, forward, reconstruction of a general complex score,
+    processing via scores and the approximate reconstruction against the
+    oracle for a seeded draw of grid, orientation set, L and variant; then
+    16-bit storage (bf16 for even seeds, fp16 for odd): the
     scores within the storage bound, their reconstruction against the
     oracle's reconstruction of the same dequantised scores (complex64
     intermediates on these paths: the FP32 tolerance)."""
@@ -448,10 +449,17 @@ def test_seeded_shape_sweep(torch_dev, seed):
     Un = (rng.standard_normal((len(n),) + shape) + 1j * rng.standard_normal((len(n),) + shape)).astype(np.complex64)
     rec = os3d.reconstruct(torch_dev.from_numpy(Un).cuda(), gb).cpu().numpy()
     assert rel(rec, O.reconstruct(Un.astype(np.complex128), ob)) < TOL, (shape, len(n), p.L)
+    Uo = O.forward(vol.astype(np.float64), ob)
+    # processing via scores (Eq. 23, soft threshold) and the approximate
+    # reconstruction (Eq. 6)
+    gp = os3d.process(f, gb, "soft_threshold", 1.5).cpu().numpy()
+    assert rel(gp, O.reconstruct(O.soft_threshold(Uo, 1.5), ob)) < TOL, (shape, len(n), p.L)
+    ga = os3d.reconstruct_approx(torch_dev.from_numpy(Un).cuda(), gb).cpu().numpy()
+    assert rel(ga, O.reconstruct_approx(Un.astype(np.complex128), ob)) < TOL, (shape, len(n), p.L)
     fmt = "bf16" if seed % 2 == 0 else "fp16"
     Uq, sc = os3d.forward(f, gb, dtype=fmt)
     Ud = os3d.unpack16(Uq, sc, fmt).cpu().numpy()
-    assert rel(Ud, O.forward(vol.astype(np.float64), ob)) < {"bf16": 4e-3, "fp16": 5e-4}[fmt], (shape, fmt)
+    assert rel(Ud, Uo) < {"bf16": 4e-3, "fp16": 5e-4}[fmt], (shape, fmt)
     rq = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
     assert rel(rq, O.reconstruct(Ud.astype(np.complex128), ob)) < TOL, (shape, fmt)
 
