@@ -431,8 +431,9 @@ def _sweep_case(seed):
 def test_seeded_shape_sweep(torch_dev, seed):
     """Bank, M, forward, reconstruction of a general complex score,
     processing via scores and the approximate reconstruction against the
-    oracle for a seeded draw of grid, orientation set, L and variant; then
-    16-bit storage (bf16 for even seeds, fp16 for odd): the
+    oracle for a seeded draw of grid, orientation set, L and variant; every
+    third draw also runs a batch of two volumes, whose elements must equal
+    the volumes run alone; then 16-bit storage (bf16 for even seeds, fp16 for odd): the
     scores within the storage bound, their reconstruction against the
     oracle's reconstruction of the same dequantised scores (complex64
     intermediates on these paths: the FP32 tolerance)."""
@@ -462,6 +463,18 @@ def test_seeded_shape_sweep(torch_dev, seed):
     assert rel(Ud, Uo) < {"bf16": 4e-3, "fp16": 5e-4}[fmt], (shape, fmt)
     rq = os3d.reconstruct(Uq, gb, scales=sc, dtype=fmt).cpu().numpy()
     assert rel(rq, O.reconstruct(Ud.astype(np.complex128), ob)) < TOL, (shape, fmt)
+    if seed % 3 == 0:
+        # a batch of two volumes: each element equals its volume run alone
+        g = torch_dev.from_numpy(inputs.tubes(shape, 2, 1.2, 0.1, 0, 4000 + seed)).cuda()
+        for dt in ("c64", fmt):
+            Ub, sb = os3d.forward(torch_dev.stack([f, g]), gb, dtype=dt)
+            U1, s1 = os3d.forward(f, gb, dtype=dt)
+            U2, s2 = os3d.forward(g, gb, dtype=dt)
+            assert torch_dev.equal(Ub[0], U1) and torch_dev.equal(Ub[1], U2), (shape, dt)
+            kw = {} if dt == "c64" else dict(dtype=dt)
+            rb = os3d.reconstruct(Ub, gb, scales=sb, **kw)
+            assert torch_dev.equal(rb[0], os3d.reconstruct(U1, gb, scales=s1, **kw)), (shape, dt)
+            assert torch_dev.equal(rb[1], os3d.reconstruct(U2, gb, scales=s2, **kw)), (shape, dt)
 
 
 @pytest.mark.parametrize("seed", range(8))
